@@ -1,0 +1,192 @@
+/*
+ * qrcp.h -- C ABI of the MI355X (gfx950) blocked randomized QR with column
+ * pivoting (BQRRP, arXiv 2507.00976) and of its unpivoted Householder QR
+ * baseline.
+ *
+ * Conventions for every entry point:
+ *  - Matrices are FP64, column-major (LAPACK layout) with an explicit leading
+ *    dimension.  Pointers documented as DEVICE point to GPU memory owned by the
+ *    caller; HOST pointers to ordinary host memory.  The library never frees or
+ *    keeps a caller pointer beyond the call.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    All device work is enqueued on it.  The blocking calls return after the
+ *    stream has drained the call's work.
+ *  - Workspace: the caller passes a DEVICE buffer of at least the size
+ *    reported by the matching *_workspace_size() query; nothing is allocated
+ *    inside the factorization calls.
+ *  - Return value: 0 on success; -i when the i-th argument is illegal (checked
+ *    on the host before any launch, LAPACK style); a positive QRCP_ERR_* code
+ *    otherwise.  qrcp_status_string() names every code.
+ *  - Indices are 0-based unless a call says otherwise (the paper's notation,
+ *    Sec. 1.3; LAPACK's one-based pivots on request).
+ */
+#ifndef QRCP_H
+#define QRCP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  QRCP_OK = 0,
+  QRCP_ERR_WORKSPACE = 1,   /* workspace missing or smaller than required       */
+  QRCP_ERR_HIP = 2,         /* a HIP runtime call or kernel launch failed        */
+  QRCP_ERR_NONFINITE = 3,   /* NaN/Inf in the input or in the sketch             */
+  QRCP_ERR_UNSUPPORTED = 4, /* valid but not implemented (e.g. m < n)            */
+  QRCP_ERR_TIMEOUT = 5      /* a cross-workgroup wait exceeded its spin limit     */
+};
+
+/* Variant choices of the method (Sec. 3 "Input and output specification":
+ * the user picks the subroutines).  Pass NULL for the defaults. */
+typedef struct qrcp_opts {
+  int32_t struct_size;        /* sizeof(qrcp_opts)                                  */
+  int32_t cholqr_passes;      /* 1 = one Cholesky QR pass as in Alg. 3 (default);
+                                 2 = Cholesky QR repeated once on Q (CholQR2)        */
+  int32_t sketch_precision;   /* 0 = FP64 sketch GEMM (default);
+                                 1 = BF16 operands, FP32 accumulation, FP64 result   */
+  int32_t trailing_precision; /* 0 = FP64 trailing update (default);
+                                 1 = FP32 operands and accumulation, FP64 storage    */
+  int32_t pivot_base;         /* 0 (default) or 1: base of the returned jpiv         */
+} qrcp_opts;
+
+/* Bytes of DEVICE workspace qrcp_factor needs for these sizes and options. */
+size_t qrcp_workspace_size(int64_t m, int64_t n, int64_t block_size, double sketch_factor,
+                           const qrcp_opts* opts);
+
+/*
+ * Blocked randomized QRCP (Alg. 1 with the LU-based wide QRCP of Alg. 2 and
+ * the preconditioned Cholesky QR + Householder reconstruction of Alg. 3).
+ *
+ *  A       DEVICE in/out, m x n, lda >= max(1,m).  On return (GEQP3 format,
+ *          Sec. 1.3): R (rank x n, upper trapezoidal) on and above the
+ *          diagonal, the Householder vectors (implicit unit head) below it for
+ *          the first `rank` columns, and the residual block A(rank:, rank:)
+ *          when rank < n.
+ *  m, n    m >= n >= 0 (m < n returns QRCP_ERR_UNSUPPORTED).
+ *  block_size   b >= 1.
+ *  sketch_factor gamma >= 1; the sketch has d = ceil(gamma*b) rows.
+ *  seed    key of the Philox4x32-10 stream that draws the Gaussian sketching
+ *          operator (Sec. 2: randomness is used once, before the loop).
+ *  tol     >= 0; block rank = leading run of |Rsk(t,t)| > tol * (largest
+ *          column norm of the initial sketch) (Sec. 2.2).  0 stops only on
+ *          exact zeros.
+ *  jpiv    DEVICE out, n int64: column t of A P is column jpiv[t] of A.
+ *  tau     DEVICE out, min(m,n) doubles: reflector scalars, 0 beyond rank.
+ *  rank    HOST out: the detected rank l.
+ *  opts    NULL = defaults.
+ *  workspace, workspace_bytes  DEVICE scratch, >= qrcp_workspace_size().
+ * Rank deficiency is not an error.  QRCP_ERR_NONFINITE leaves A partially
+ * factored.
+ */
+int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size,
+                double sketch_factor, uint64_t seed, double tol, int64_t* jpiv, double* tau,
+                int64_t* rank, const qrcp_opts* opts, void* workspace, size_t workspace_bytes,
+                void* stream);
+
+/* Unpivoted blocked Householder QR (GEQRF format), the performance baseline
+ * the canonical FLOP rate is compared against (Sec. 1.4, Sec. 7).  A is m x n
+ * DEVICE (m >= n), tau DEVICE min(m,n), nb = panel width. */
+size_t qrcp_geqrf_workspace_size(int64_t m, int64_t n, int64_t nb);
+int qrcp_geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, int64_t nb,
+               void* workspace, size_t workspace_bytes, void* stream);
+
+const char* qrcp_status_string(int status);
+/* Text of the last HIP error seen by the calling thread ("" if none). */
+const char* qrcp_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Step entry points: each runs one step of the per-block loop with the same
+ * kernels qrcp_factor uses, so every step can be checked on its own.
+ * ---------------------------------------------------------------------- */
+
+/* S (d x m, N(0,1) entries) stored transposed: St is m x d, ld = ldst >= m.
+ * Entry S(2p, j), S(2p+1, j) = Box-Muller pair of Philox4x32-10 block
+ * counter (j, p, 0, 0), key (seed lo32, seed hi32):
+ *   u1 = (2*(w01 >> 12) + 1) 2^-53,  u2 = (w23 >> 11) 2^-53,
+ *   S(2p,j) = sqrt(-2 ln u1) cos(2 pi u2), S(2p+1,j) = sqrt(-2 ln u1) sin(2 pi u2)
+ * (Alg. 1 sampling step; Sec. 3 "Initial sketching details"). */
+int qrcp_sketch_operator(double* St, int64_t m, int64_t d, int64_t ldst, uint64_t seed,
+                         void* stream);
+/* Raw Philox4x32-10 blocks: ctr DEVICE count x 4 uint32, out DEVICE count x 4. */
+int qrcp_philox(const uint32_t* ctr, int64_t count, uint32_t key0, uint32_t key1, uint32_t* out,
+                void* stream);
+/* M^sk = S A (Alg. 1 sketching step).  A DEVICE m x n (lda), Msk DEVICE d x n
+ * (ldmsk >= d).  precision: 0 FP64, 1 BF16 operands with FP32 accumulation.
+ * workspace >= m*d doubles (holds S^T). */
+int qrcp_sketch(const double* A, int64_t m, int64_t n, int64_t lda, int64_t d, uint64_t seed,
+                int32_t precision, double* Msk, int64_t ldmsk, void* workspace,
+                size_t workspace_bytes, void* stream);
+
+/* Pivots of a wide sketch by GETRF on its transpose (Alg. 2).  Msk DEVICE
+ * d x ni (ld >= d), read only.  Outputs (DEVICE): ipiv[min(d,ni)] in LAPACK
+ * swap format (0-based positions), jsk[ni] the converted permutation (column t
+ * of the permuted sketch is column jsk[t]).  Ties in |pivot| go to the
+ * smallest current position.  workspace >= qrcp_lu_workspace_size(). */
+size_t qrcp_lu_workspace_size(int64_t d, int64_t ni);
+int qrcp_lu_pivots(const double* Msk, int64_t d, int64_t ni, int64_t ldmsk, int64_t* ipiv,
+                   int64_t* jsk, void* workspace, size_t workspace_bytes, void* stream);
+
+/* GEQRF of a permuted wide sketch (Alg. 2 last step): B DEVICE d x ni (ld >=
+ * d) holding the columns in pivot order, read only; R DEVICE d x ni (ldr >= d)
+ * receives the upper trapezoidal R (exact zeros below the diagonal). */
+size_t qrcp_sketch_qr_workspace_size(int64_t d, int64_t ni);
+int qrcp_sketch_qr(const double* B, int64_t d, int64_t ni, int64_t ldb, double* R, int64_t ldr,
+                   void* workspace, size_t workspace_bytes, void* stream);
+
+/* Preconditioned Cholesky QR of a panel (Alg. 3 first two steps):
+ * P DEVICE mi x k (ldp) is overwritten by Q = P Rs^{-1} Rc^{-1}, Rs DEVICE k x k
+ * upper (ldrs), Rc DEVICE k x k (ldrc) receives the Cholesky factor, *keff
+ * (HOST) the number of columns factored before a Cholesky breakdown (== k when
+ * none).  passes = 1 or 2.  workspace >= qrcp_panel_workspace_size(). */
+size_t qrcp_panel_workspace_size(int64_t mi, int64_t k);
+int qrcp_cholqr(double* P, int64_t mi, int64_t k, int64_t ldp, const double* Rs, int64_t ldrs,
+                double* Rc, int64_t ldrc, int32_t passes, int64_t* keff, void* workspace,
+                size_t workspace_bytes, void* stream);
+
+/* Householder reconstruction of an orthonormal Q (Alg. 3 third step, after
+ * Ballard et al.'s modified LU): Q DEVICE mi x k (ldq) is overwritten by Y
+ * (strictly below the diagonal; the unit diagonal is implicit) and U on and
+ * above it; tau DEVICE k, dsig DEVICE k (the sign vector D).  The first k
+ * columns of H_0 ... H_{k-1} equal Q diag(D). */
+int qrcp_reconstruct(double* Q, int64_t mi, int64_t k, int64_t ldq, double* tau, double* dsig,
+                     void* workspace, size_t workspace_bytes, void* stream);
+
+/* C <- (H_0 ... H_{k-1})^T C (ORMQR left/transpose, Sec. 2.4) with Y DEVICE
+ * mi x k (unit lower trapezoidal read from below the diagonal, ldy), tau DEVICE
+ * k, C DEVICE mi x nc (ldc).  precision 0 = FP64, 1 = FP32 GEMMs. */
+size_t qrcp_apply_qt_workspace_size(int64_t mi, int64_t k, int64_t nc);
+int qrcp_apply_qt(const double* Y, int64_t mi, int64_t k, int64_t ldy, const double* tau,
+                  double* C, int64_t nc, int64_t ldc, int32_t precision, void* workspace,
+                  size_t workspace_bytes, void* stream);
+
+/* Sketch update (Alg. 1 last step, Sec. 3 "Sample update"):
+ * Out(0:b, :) = Rsk12 - Rsk11 R11^{-1} R12 and Out(b:d, :) = Rsk22 are formed in
+ * place in Rsk: Rsk DEVICE d x (b + nt) (ld), R11 DEVICE b x b upper (ldr11),
+ * R12 DEVICE b x nt (ldr12).  On return Rsk(:, b:b+nt) holds the updated
+ * sketch. */
+int qrcp_sketch_update(double* Rsk, int64_t d, int64_t b, int64_t nt, int64_t ldrsk,
+                       const double* R11, int64_t ldr11, const double* R12, int64_t ldr12,
+                       void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Stage timing (instrumentation, not part of the method).  mode 0 = off,
+ * 1 = time only the trailing-update product C -= Y W (the dominant kernel),
+ * 2 = time every stage of the loop.  Enabling clears earlier records.  HIP
+ * events are recorded on the stream of each call; qrcp_profile_read() waits
+ * for them and returns the summed device time (ms), the number of timed
+ * launches and the algorithmic flops attributed to the stage.  Not thread
+ * safe: one profiling client per process.
+ * ---------------------------------------------------------------------- */
+int qrcp_profile_enable(int32_t mode);
+int32_t qrcp_profile_num_stages(void);
+const char* qrcp_profile_stage_name(int32_t stage);
+int qrcp_profile_read(int32_t stage, double* ms, int64_t* count, double* flops);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QRCP_H */

@@ -369,7 +369,7 @@ class Result:
 def bqrrp(a: np.ndarray, b: int, gamma: float = 1.25, seed: int = 42, tol: float = 0.0,
           cholqr_passes: int = 1, qrcp_wide: str = "lu", sketch_precision: str = "f64",
           trailing_precision: str = "f64", msk: np.ndarray | None = None,
-          trace_sketch: bool = False) -> Result:
+          trace_sketch: bool = False, max_blocks: int | None = None) -> Result:
     """BQRRP with LU-based qrcp_wide and Cholesky-QR qr_tall.
 
     Per block i (s = i b, n_i = n - s, m_i = m - s, k_max = min(b, n_i, m_i)):
@@ -445,12 +445,19 @@ def bqrrp(a: np.ndarray, b: int, gamma: float = 1.25, seed: int = 42, tol: float
             t = larft(y, tk)
             cmat = a[s:, s + k:]
             if trailing_precision == "f32":
+                # the two products of the update run in FP32 (operands rounded
+                # to FP32, FP32 accumulation); C itself stays FP64
                 y32, t32, c32 = (x.astype(np.float32) for x in (y, t, cmat))
-                w = (t32.T @ (y32.T @ c32))
-                a[s:, s + k:] = (c32 - y32 @ w).astype(np.float64)
+                w = t32.T @ (y32.T @ c32)
+                a[s:, s + k:] = cmat - (y32 @ w).astype(np.float64)
             else:
                 a[s:, s + k:] = apply_qt(y, t, cmat)
         if k < kmax or c >= n:
+            res.rank = s + k
+            return res
+        if max_blocks is not None and len(res.trace) >= max_blocks:
+            # a leading sample of the loop (used to compare large problems
+            # block-row by block-row); the trailing block is left updated
             res.rank = s + k
             return res
         # ---- sketch update (Alg. 1 last step; Sec. 3 "Sample update") ----

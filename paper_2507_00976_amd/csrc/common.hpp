@@ -1,0 +1,97 @@
+// Shared device/host helpers of the gfx950 QRCP library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/qrcp.h"
+
+namespace qrcp {
+
+using i64 = int64_t;
+
+// Records the HIP error text for qrcp_last_error().
+void note_hip_error(hipError_t e, const char* what);
+
+#define QRCP_HIP(call)                                  \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) {                             \
+      ::qrcp::note_hip_error(e_, #call);                \
+      return QRCP_ERR_HIP;                              \
+    }                                                   \
+  } while (0)
+
+#define QRCP_LAUNCHED(what)                             \
+  do {                                                  \
+    hipError_t e_ = hipGetLastError();                  \
+    if (e_ != hipSuccess) {                             \
+      ::qrcp::note_hip_error(e_, what);                 \
+      return QRCP_ERR_HIP;                              \
+    }                                                   \
+  } while (0)
+
+#define QRCP_TRY(expr)              \
+  do {                              \
+    int rc_ = (expr);               \
+    if (rc_ != QRCP_OK) return rc_; \
+  } while (0)
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Block-wide sum for blockDim.x = NT (multiple of 64).  `red` needs NT/64
+// doubles of shared memory.  Every thread gets the result.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) s += red[i];
+  return s;
+}
+
+// Bit-level access for the cross-workgroup record exchange.
+__device__ __forceinline__ uint64_t dbits(double x) { return __double_as_longlong(x); }
+__device__ __forceinline__ double bitsd(uint64_t x) { return __longlong_as_double((long long)x); }
+
+__device__ __forceinline__ void store_agent(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t load_agent(uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_agent_i32(int* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int load_agent_i32(int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Launches a kernel whose workgroups wait on each other: checks that the whole
+// grid fits on the device at once (occupancy x compute units) and launches it
+// with an ordinary launch.  Every wait in such a kernel is bounded by
+// kSpinLimit, so a grid that is not resident ends in QRCP_ERR_TIMEOUT.
+int launch_resident(const void* fn, dim3 grid, dim3 block, void** params, size_t smem,
+                    hipStream_t st);
+
+// Spin limit of every cross-workgroup wait: far above any legitimate wait,
+// it turns a lost partner into QRCP_ERR_TIMEOUT instead of a hung GPU.
+constexpr long kSpinLimit = 1L << 22;
+
+}  // namespace qrcp

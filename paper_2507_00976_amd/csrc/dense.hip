@@ -1,0 +1,545 @@
+// Sketching operator and the small dense kernels of the panel (triangular
+// inverses, Cholesky, the sign-modified LU of the reconstruction, copies).
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace qrcp {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the
+// multiply/xor S-box on the 4-word counter, the 2-word key advanced by the
+// Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1,
+                   (uint32_t)p0);
+  }
+  return c;
+}
+
+__global__ void philox_kernel(const uint32_t* ctr, long count, uint32_t k0, uint32_t k1,
+                              uint32_t* out) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  uint4 c = make_uint4(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3]);
+  c = philox4x32_10(c, k0, k1);
+  out[4 * i] = c.x;
+  out[4 * i + 1] = c.y;
+  out[4 * i + 2] = c.z;
+  out[4 * i + 3] = c.w;
+}
+
+// S^T (m x d, ld): S(2p, j), S(2p+1, j) from block (j, p, 0, 0) by Box-Muller.
+__global__ void sketch_operator_kernel(double* St, long m, int d, long ld, uint32_t k0,
+                                       uint32_t k1) {
+  const long j = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (j >= m) return;
+  const uint4 x = philox4x32_10(make_uint4((uint32_t)j, (uint32_t)p, 0u, 0u), k0, k1);
+  const uint64_t w01 = ((uint64_t)x.y << 32) | x.x;
+  const uint64_t w23 = ((uint64_t)x.w << 32) | x.z;
+  const double u1 = ((double)(w01 >> 12) * 2.0 + 1.0) * 0x1p-53;
+  const double u2 = (double)(w23 >> 11) * 0x1p-53;
+  const double rad = sqrt(-2.0 * log(u1));
+  const double ang = (2.0 * 3.141592653589793) * u2;
+  St[j + (long)(2 * p) * ld] = rad * cos(ang);
+  if (2 * p + 1 < d) St[j + (long)(2 * p + 1) * ld] = rad * sin(ang);
+}
+
+int launch_sketch_operator(double* St, i64 m, int d, i64 ldst, uint64_t seed, hipStream_t st) {
+  if (m <= 0 || d <= 0) return QRCP_OK;
+  dim3 grid((m + 255) / 256, (d + 1) / 2);
+  hipLaunchKernelGGL(sketch_operator_kernel, grid, dim3(256), 0, st, St, m, d, ldst,
+                     (uint32_t)seed, (uint32_t)(seed >> 32));
+  QRCP_LAUNCHED("sketch_operator");
+  return QRCP_OK;
+}
+
+int launch_philox(const uint32_t* ctr, i64 count, uint32_t k0, uint32_t k1, uint32_t* out,
+                  hipStream_t st) {
+  if (count <= 0) return QRCP_OK;
+  hipLaunchKernelGGL(philox_kernel, dim3((count + 255) / 256), dim3(256), 0, st, ctr, count, k0,
+                     k1, out);
+  QRCP_LAUNCHED("philox");
+  return QRCP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// X = R^{-1}, R upper triangular n x n.  One wave per column j: column-oriented
+// back substitution on x = e_j held in registers (lane l owns rows l + 64 s).
+// ---------------------------------------------------------------------------
+template <int NR>
+__global__ __launch_bounds__(256) void trinv_upper_kernel(const double* R, long ldr, int n,
+                                                          double* X, long ldx) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= n) return;
+  double x[NR];
+#pragma unroll
+  for (int s = 0; s < NR; ++s) x[s] = (s * 64 + lane == j) ? 1.0 : 0.0;
+  for (int i = j; i >= 0; --i) {
+    const int si = i >> 6, li = i & 63;
+    double xi = 0.0;
+#pragma unroll
+    for (int s = 0; s < NR; ++s)
+      if (s == si) xi = __shfl(x[s], li, 64);
+    xi = xi / R[i + (long)i * ldr];
+#pragma unroll
+    for (int s = 0; s < NR; ++s) {
+      const int r = s * 64 + lane;
+      if (r == i) x[s] = xi;
+      else if (r < i) x[s] -= xi * R[r + (long)i * ldr];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < NR; ++s) {
+    const int r = s * 64 + lane;
+    if (r < n) X[r + (long)j * ldx] = (r <= j) ? x[s] : 0.0;
+  }
+}
+
+int launch_trinv_upper(const double* R, i64 ldr, int n, double* X, i64 ldx, hipStream_t st) {
+  if (n <= 0) return QRCP_OK;
+  dim3 grid((n + 3) / 4), block(256);
+  if (n <= 64) hipLaunchKernelGGL(trinv_upper_kernel<1>, grid, block, 0, st, R, ldr, n, X, ldx);
+  else if (n <= 256) hipLaunchKernelGGL(trinv_upper_kernel<4>, grid, block, 0, st, R, ldr, n, X, ldx);
+  else if (n <= 512) hipLaunchKernelGGL(trinv_upper_kernel<8>, grid, block, 0, st, R, ldr, n, X, ldx);
+  else if (n <= 1024) hipLaunchKernelGGL(trinv_upper_kernel<16>, grid, block, 0, st, R, ldr, n, X, ldx);
+  else return QRCP_ERR_UNSUPPORTED;
+  QRCP_LAUNCHED("trinv_upper");
+  return QRCP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Compact WY factor from Y^T Y and tau (UT transform: T^{-1} = diag(1/tau) +
+// strictly-upper(Y^T Y)).  A zero tau (H_j = I) decouples index j: its row and
+// column are cleared and T(j,j) = 0 afterwards.
+// ---------------------------------------------------------------------------
+__global__ void ut_prepare_kernel(double* G, long ldg, const double* tau, int n) {
+  const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (idx >= (long)n * n) return;
+  const int i = idx % n, j = idx / n;
+  double* g = G + i + (long)j * ldg;
+  if (i > j) { *g = 0.0; return; }
+  if (tau[i] == 0.0 || tau[j] == 0.0) { *g = (i == j) ? 1.0 : 0.0; return; }
+  if (i == j) *g = 1.0 / tau[i];
+}
+
+__global__ void ut_zero_diag_kernel(double* T, long ldt, const double* tau, int n) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n && tau[j] == 0.0) T[j + (long)j * ldt] = 0.0;
+}
+
+int launch_ut_tinv(double* G, i64 ldg, const double* tau, int n, hipStream_t st) {
+  if (n <= 0) return QRCP_OK;
+  hipLaunchKernelGGL(ut_prepare_kernel, dim3(((long)n * n + 255) / 256), dim3(256), 0, st, G, ldg,
+                     tau, n);
+  QRCP_LAUNCHED("ut_prepare");
+  return QRCP_OK;
+}
+
+int launch_ut_zero_diag(double* T, i64 ldt, const double* tau, int n, hipStream_t st) {
+  hipLaunchKernelGGL(ut_zero_diag_kernel, dim3((n + 255) / 256), dim3(256), 0, st, T, ldt, tau, n);
+  QRCP_LAUNCHED("ut_zero_diag");
+  return QRCP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Blocked right-looking factorizations of a small square matrix (n <= 1024) by
+// one 256-thread workgroup.  Per 32-column step: the 32 x 32 diagonal block is
+// factored in LDS by one wave, the off-diagonal panels by one thread per row or
+// column, and the trailing block is updated in 64 x 64 tiles on the FP64
+// matrix cores (LDS-staged operands).
+// ---------------------------------------------------------------------------
+constexpr int SB = 32;
+constexpr int TT = 64;  // trailing tile
+
+typedef double dv4 __attribute__((ext_vector_type(4)));
+
+// C(0:M, 0:N) (-)= A B for one tile: A is M x kk staged as sA[t][i], B is
+// kk x N staged as sB[t][j] (kk <= 32, M, N <= 64).  Executed by the 4 waves
+// of the 256-thread workgroup on the FP64 matrix cores.  assign: C = A B,
+// else C -= A B.
+__device__ __forceinline__ void tile_mm(double* C, long ldc, int M, int N, int kk,
+                                        const double (*sA)[TT], const double (*sB)[TT],
+                                        bool assign) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w & 1, wn = w >> 1;
+  dv4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = dv4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < kk; k0 += 4) {
+    const int kr = k0 + (lane >> 4);
+    double af[2], bf[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) af[a] = (kr < kk) ? sA[kr][wm * 32 + a * 16 + (lane & 15)] : 0.0;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) bf[b] = (kr < kk) ? sB[kr][wn * 32 + b * 16 + (lane & 15)] : 0.0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[b], af[a], acc[a][b], 0, 0, 0);
+  }
+  // block of C^T: lane holds C(i = lane%16, j = 4 r + lane/16)
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int i = wm * 32 + a * 16 + (lane & 15);
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = wn * 32 + b * 16 + 4 * r + (lane >> 4);
+        if (i < M && j < N) {
+          double* c = C + i + (long)j * ldc;
+          *c = assign ? acc[a][b][r] : *c - acc[a][b][r];
+        }
+      }
+  }
+}
+
+// Generic tiled product over a rows x cols output: C (-)= A B with A(i, t)
+// and B(t, j) read through accessors (t < kk <= 32).  upper_only skips tiles
+// strictly below the diagonal.  Tiles are staged in LDS one at a time.
+template <typename FA, typename FB>
+__device__ __forceinline__ void tiled_mm(double* C, long ldc, int rows, int cols, int kk,
+                                         bool upper_only, bool assign, FA fa, FB fb,
+                                         double (*sA)[TT], double (*sB)[TT]) {
+  const int tid = threadIdx.x;
+  const int ntr = (rows + TT - 1) / TT, ntc = (cols + TT - 1) / TT;
+  for (int ti = 0; ti < ntr * ntc; ++ti) {
+    const int tr = ti % ntr, tc = ti / ntr;
+    if (upper_only && tr > tc) continue;   // uniform
+    const int r0 = tr * TT, c0 = tc * TT;
+    const int M = min(TT, rows - r0), N = min(TT, cols - c0);
+    __syncthreads();
+    for (int e = tid; e < SB * TT; e += blockDim.x) {
+      const int t = e / TT, x = e % TT;
+      sA[t][x] = (t < kk && x < M) ? fa(r0 + x, t) : 0.0;
+      sB[t][x] = (t < kk && x < N) ? fb(t, c0 + x) : 0.0;
+    }
+    __syncthreads();
+    tile_mm(C + r0 + (long)c0 * ldc, ldc, M, N, kk, sA, sB, assign);
+  }
+  __syncthreads();
+}
+
+// One wave: X = inverse of the upper triangle of D (nb x nb) into sX.
+__device__ __forceinline__ void wave_inv_upper(const double (*D)[SB + 1], double (*X)[SB + 1], int nb) {
+  const int j = threadIdx.x & 63;
+  if (j < nb) {
+    for (int i = nb - 1; i >= 0; --i) {
+      double v;
+      if (i > j) {
+        v = 0.0;
+      } else if (i == j) {
+        v = 1.0 / D[i][i];
+      } else {
+        double sacc = 0.0;
+        for (int l = i + 1; l <= j; ++l) sacc += D[i][l] * X[l][j];
+        v = -sacc / D[i][i];
+      }
+      X[i][j] = v;
+    }
+  }
+}
+
+// One wave: X = inverse of the unit lower triangle of D (nb x nb) into sX.
+__device__ __forceinline__ void wave_inv_unit_lower(const double (*D)[SB + 1], double (*X)[SB + 1],
+                                                    int nb) {
+  const int j = threadIdx.x & 63;
+  if (j < nb) {
+    for (int i = 0; i < nb; ++i) {
+      double v;
+      if (i < j) {
+        v = 0.0;
+      } else if (i == j) {
+        v = 1.0;
+      } else {
+        double sacc = 0.0;
+        for (int l = j; l < i; ++l) sacc += D[i][l] * X[l][j];
+        v = -sacc;
+      }
+      X[i][j] = v;
+    }
+  }
+}
+
+// Cholesky G = R^T R, upper.  *info = columns factored (n if no breakdown).
+__global__ __launch_bounds__(256) void potrf_upper_kernel(double* G, long ldg, int n, int* info) {
+  __shared__ double sD[SB][SB + 1];
+  __shared__ double sX[SB][SB + 1];
+  __shared__ double sA[SB][TT];
+  __shared__ double sB[SB][TT];
+  __shared__ int brk;
+  const int tid = threadIdx.x;
+  if (tid == 0) brk = -1;
+  for (int p0 = 0; p0 < n; p0 += SB) {
+    const int nb = min(SB, n - p0);
+    __syncthreads();
+    for (int e = tid; e < SB * SB; e += blockDim.x) {
+      const int tr = e % SB, tc = e / SB;
+      if (tr < nb && tc < nb) sD[tr][tc] = (tr <= tc) ? G[(p0 + tr) + (long)(p0 + tc) * ldg] : 0.0;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      const int lane = tid;
+      for (int t = 0; t < nb; ++t) {
+        const double dd = sD[t][t];
+        if (!(dd > 0.0)) {
+          if (lane == 0) brk = p0 + t;
+          break;
+        }
+        const double r = sqrt(dd);
+        __builtin_amdgcn_wave_barrier();
+        if (lane == t) sD[t][t] = r;
+        if (lane > t && lane < nb) sD[t][lane] /= r;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        if (lane > t && lane < nb) {
+          const double u = sD[t][lane];
+          for (int rr = t + 1; rr <= lane; ++rr) sD[rr][lane] -= sD[t][rr] * u;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < SB * SB; e += blockDim.x) {
+      const int tr = e % SB, tc = e / SB;
+      if (tr < nb && tc < nb && tr <= tc) G[(p0 + tr) + (long)(p0 + tc) * ldg] = sD[tr][tc];
+    }
+    if (brk >= 0) break;
+    const int rest = n - p0 - nb;
+    if (rest > 0) {
+      if (tid < 64) wave_inv_upper(sD, sX, nb);
+      __syncthreads();
+      // row panel R12 = R11^{-T} G12 (in place): A(i, t) = R11^{-1}(t, i)
+      double* g12 = G + p0 + (long)(p0 + nb) * ldg;
+      tiled_mm(g12, ldg, nb, rest, nb, false, true,
+               [&](int i, int t) { return sX[t][i]; },
+               [&](int t, int j) { return g12[t + (long)j * ldg]; }, sA, sB);
+      // trailing update of the upper triangle: G22 -= R12^T R12
+      tiled_mm(G + (p0 + nb) + (long)(p0 + nb) * ldg, ldg, rest, rest, nb, true, false,
+               [&](int i, int t) { return g12[t + (long)i * ldg]; },
+               [&](int t, int j) { return g12[t + (long)j * ldg]; }, sA, sB);
+    }
+  }
+  __syncthreads();
+  const int done = (brk >= 0) ? brk : n;
+  for (long e = tid; e < (long)n * n; e += blockDim.x) {
+    const int r = e % n, c = e / n;
+    if (r > c) G[r + (long)c * ldg] = 0.0;
+  }
+  if (tid == 0) *info = done;
+}
+
+int launch_potrf_upper(double* G, i64 ldg, int n, int* info_dev, hipStream_t st) {
+  hipLaunchKernelGGL(potrf_upper_kernel, dim3(1), dim3(256), 0, st, G, ldg, n, info_dev);
+  QRCP_LAUNCHED("potrf_upper");
+  return QRCP_OK;
+}
+
+// Sign-modified LU without pivoting of Q(0:k, 0:k) (Householder reconstruction):
+// at step j, D_j = -sgn(Q(j,j)) (sgn(0) = +1), Q(j,j) -= D_j, the column below
+// is divided by the new pivot and the trailing block updated.
+__global__ __launch_bounds__(256) void headlu_kernel(double* Q, long ldq, int k, double* dsig) {
+  __shared__ double sD[SB][SB + 1];
+  __shared__ double sX[SB][SB + 1];
+  __shared__ double sA[SB][TT];
+  __shared__ double sB[SB][TT];
+  const int tid = threadIdx.x;
+  for (int p0 = 0; p0 < k; p0 += SB) {
+    const int nb = min(SB, k - p0);
+    __syncthreads();
+    for (int e = tid; e < SB * SB; e += blockDim.x) {
+      const int tr = e % SB, tc = e / SB;
+      if (tr < nb && tc < nb) sD[tr][tc] = Q[(p0 + tr) + (long)(p0 + tc) * ldq];
+    }
+    __syncthreads();
+    if (tid < 64) {
+      const int lane = tid;  // lane = row of the diagonal block
+      for (int t = 0; t < nb; ++t) {
+        const double a = sD[t][t];
+        const double dj = (a >= 0.0) ? -1.0 : 1.0;
+        const double piv = a - dj;
+        __builtin_amdgcn_wave_barrier();
+        if (lane == t) {
+          sD[t][t] = piv;
+          dsig[p0 + t] = dj;
+        }
+        if (lane > t && lane < nb) sD[lane][t] /= piv;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        if (lane > t && lane < nb) {
+          const double l = sD[lane][t];
+          for (int c = t + 1; c < nb; ++c) sD[lane][c] -= l * sD[t][c];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < SB * SB; e += blockDim.x) {
+      const int tr = e % SB, tc = e / SB;
+      if (tr < nb && tc < nb) Q[(p0 + tr) + (long)(p0 + tc) * ldq] = sD[tr][tc];
+    }
+    const int rest = k - p0 - nb;
+    if (rest > 0) {
+      double* a21 = Q + (p0 + nb) + (long)p0 * ldq;   // rows below the block
+      double* a12 = Q + p0 + (long)(p0 + nb) * ldq;   // columns right of the block
+      // L21 = A21 U11^{-1}
+      if (tid < 64) wave_inv_upper(sD, sX, nb);
+      __syncthreads();
+      tiled_mm(a21, ldq, rest, nb, nb, false, true,
+               [&](int i, int t) { return a21[i + (long)t * ldq]; },
+               [&](int t, int j) { return sX[t][j]; }, sA, sB);
+      // U12 = L11^{-1} A12
+      if (tid < 64) wave_inv_unit_lower(sD, sX, nb);
+      __syncthreads();
+      tiled_mm(a12, ldq, nb, rest, nb, false, true,
+               [&](int i, int t) { return sX[i][t]; },
+               [&](int t, int j) { return a12[t + (long)j * ldq]; }, sA, sB);
+      // A22 -= L21 U12
+      tiled_mm(Q + (p0 + nb) + (long)(p0 + nb) * ldq, ldq, rest, rest, nb, false, false,
+               [&](int i, int t) { return a21[i + (long)t * ldq]; },
+               [&](int t, int j) { return a12[t + (long)j * ldq]; }, sA, sB);
+    }
+  }
+}
+
+int launch_headlu(double* Q, i64 ldq, int k, double* dsig, hipStream_t st) {
+  if (k <= 0) return QRCP_OK;
+  hipLaunchKernelGGL(headlu_kernel, dim3(1), dim3(256), 0, st, Q, ldq, k, dsig);
+  QRCP_LAUNCHED("headlu");
+  return QRCP_OK;
+}
+
+__global__ void tau_from_u_kernel(const double* Q, long ldq, int k, const double* dsig,
+                                  double* tau) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < k) tau[j] = -dsig[j] * Q[j + (long)j * ldq];
+}
+
+int launch_tau_from_u(const double* Q, i64 ldq, int k, const double* dsig, double* tau,
+                      hipStream_t st) {
+  if (k <= 0) return QRCP_OK;
+  hipLaunchKernelGGL(tau_from_u_kernel, dim3((k + 255) / 256), dim3(256), 0, st, Q, ldq, k, dsig,
+                     tau);
+  QRCP_LAUNCHED("tau_from_u");
+  return QRCP_OK;
+}
+
+__global__ void write_r11_kernel(const double* P, long ldp, int k, const double* dsig, double* A,
+                                 long lda) {
+  const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (idx >= (long)k * k) return;
+  const int i = idx % k, j = idx / k;
+  if (i <= j) A[i + (long)j * lda] = dsig[i] * P[i + (long)j * ldp];
+}
+
+int launch_write_r11(const double* P, i64 ldp, int k, const double* dsig, double* A, i64 lda,
+                     hipStream_t st) {
+  if (k <= 0) return QRCP_OK;
+  hipLaunchKernelGGL(write_r11_kernel, dim3(((long)k * k + 255) / 256), dim3(256), 0, st, P, ldp,
+                     k, dsig, A, lda);
+  QRCP_LAUNCHED("write_r11");
+  return QRCP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Copies and fills (2D, column-major).  One thread per element, rows fastest.
+// ---------------------------------------------------------------------------
+__global__ void copy2d_kernel(const double* src, long lds, double* dst, long ldd, long rows,
+                              long cols, int mode) {
+  const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const long i = idx % rows, j = idx / rows;
+  double v = src[i + j * lds];
+  if (mode == 1 && i > j) v = 0.0;  // upper trapezoid only
+  dst[i + j * ldd] = v;
+}
+
+int launch_copy2d(const double* src, i64 lds, double* dst, i64 ldd, i64 rows, i64 cols,
+                  hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return QRCP_OK;
+  hipLaunchKernelGGL(copy2d_kernel, dim3((rows * cols + 255) / 256), dim3(256), 0, st, src, lds,
+                     dst, ldd, rows, cols, 0);
+  QRCP_LAUNCHED("copy2d");
+  return QRCP_OK;
+}
+
+int launch_triu_copy(const double* src, i64 lds, double* dst, i64 ldd, i64 rows, i64 cols,
+                     hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return QRCP_OK;
+  hipLaunchKernelGGL(copy2d_kernel, dim3((rows * cols + 255) / 256), dim3(256), 0, st, src, lds,
+                     dst, ldd, rows, cols, 1);
+  QRCP_LAUNCHED("triu_copy");
+  return QRCP_OK;
+}
+
+__global__ void fill_kernel(double* dst, long ld, long rows, long cols, double v) {
+  const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  dst[idx % rows + (idx / rows) * ld] = v;
+}
+
+int launch_fill(double* dst, i64 ld, i64 rows, i64 cols, double v, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return QRCP_OK;
+  hipLaunchKernelGGL(fill_kernel, dim3((rows * cols + 255) / 256), dim3(256), 0, st, dst, ld, rows,
+                     cols, v);
+  QRCP_LAUNCHED("fill");
+  return QRCP_OK;
+}
+
+__global__ void fill_u64_kernel(uint64_t* dst, long count, uint64_t v) {
+  const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (idx < count) dst[idx] = v;
+}
+
+int launch_fill_u64(uint64_t* dst, i64 count, uint64_t v, hipStream_t st) {
+  if (count <= 0) return QRCP_OK;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3((count + 255) / 256), dim3(256), 0, st, dst, count, v);
+  QRCP_LAUNCHED("fill_u64");
+  return QRCP_OK;
+}
+
+// identity diagonal: dst(i,i) = 1 for a square n x n already zero-filled
+__global__ void set_diag_kernel(double* dst, long ld, long n, double v) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i < n) dst[i + i * ld] = v;
+}
+
+int launch_set_identity(double* dst, i64 ld, i64 n, hipStream_t st) {
+  QRCP_TRY(launch_fill(dst, ld, n, n, 0.0, st));
+  hipLaunchKernelGGL(set_diag_kernel, dim3((n + 255) / 256), dim3(256), 0, st, dst, ld, n, 1.0);
+  QRCP_LAUNCHED("set_diag");
+  return QRCP_OK;
+}
+
+__global__ void any_nonfinite_kernel(const double* X, long ld, long rows, long cols, int* flag) {
+  const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  bool bad = false;
+  if (idx < rows * cols) bad = !isfinite(X[idx % rows + (idx / rows) * ld]);
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+int launch_any_nonfinite(const double* X, i64 ld, i64 rows, i64 cols, int* flag, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return QRCP_OK;
+  hipLaunchKernelGGL(any_nonfinite_kernel, dim3((rows * cols + 255) / 256), dim3(256), 0, st, X,
+                     ld, rows, cols, flag);
+  QRCP_LAUNCHED("any_nonfinite");
+  return QRCP_OK;
+}
+
+}  // namespace qrcp

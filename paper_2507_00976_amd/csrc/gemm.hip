@@ -1,0 +1,432 @@
+// Tiled matrix-core GEMMs for gfx950.
+//
+//   C(M x N) = alpha * op(A) op(B) + beta * C        (column-major everywhere)
+//
+// op(A) is M x K: A stored M x K (TA = false) or K x M (TA = true).
+// op(B) is K x N: B stored K x N (TB = false) or N x K (TB = true).
+// Options used by the QRCP loop:
+//  * `bcol`: column indirection of op(B) (TB = false only) -- used to read R12
+//    in logical column order from physically unmoved columns.
+//  * split-K with a fixed-order reduction (deterministic results).
+//
+// Compute types: FP64 (v_mfma_f64_16x16x4f64), FP32 (v_mfma_f32_16x16x4f32,
+// operands rounded from FP64 on load), and BF16 operands with FP32
+// accumulation (v_mfma_f32_16x16x16bf16_1k) for the reduced-precision sketch.
+//
+// Tile: BM x BN per 256-thread workgroup = 2 x 2 waves, each wave owns a
+// (BM/2) x (BN/2) block of 16 x 16 MFMA tiles.  The MFMA is issued with the
+// operands swapped (it computes the 16x16 block of C^T), so each lane's four
+// results are four *columns* of one row group and 16 consecutive lanes hold
+// 16 consecutive rows of a column: the stores are 128-byte contiguous.
+#include <cstdlib>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace qrcp {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef short s4v __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+
+template <>
+struct Mfma<double> {
+  using acc_t = d4v;
+  static constexpr int KS = 4;  // k per instruction
+  __device__ static acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+  __device__ static acc_t run(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // result r of lane l is row 4 r + l/16, column l%16 of the 16x16 block
+  __device__ static int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+
+template <>
+struct Mfma<float> {
+  using acc_t = f4v;
+  static constexpr int KS = 4;
+  __device__ static acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static acc_t run(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // result r of lane l is row 4 (l/16) + r, column l%16 of the 16x16 block
+  __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+// FP64 -> FP32 (RNE) -> BF16 (RNE) bits.
+__device__ __forceinline__ unsigned short to_bf16_bits(double x) {
+  float f = (float)x;
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+template <typename T>
+__device__ __forceinline__ T cvt(double x) {
+  return (T)x;
+}
+
+template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, typename T>
+__device__ __forceinline__ void gemm_body(const GemmArgs& g) {
+  constexpr int NTH = 64 * WGM * WGN;
+  constexpr int BK = 16;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int LA = BM * BK / NTH, LB = BN * BK / NTH;
+  using MF = Mfma<T>;
+  using acc_t = typename MF::acc_t;
+
+  // double-buffered operand tiles, padded against bank conflicts of the
+  // transposed stores
+  __shared__ T sA[2][BK][BM + 1];
+  __shared__ T sB[2][BK][BN + 1];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WGM, wn = wave / WGM;
+  const int i0 = blockIdx.y * BM, j0 = blockIdx.x * BN;
+  const int M = g.M, N = g.N;
+  const long kbeg = (long)blockIdx.z * g.kchunk;
+  const long kend = min((long)g.K, kbeg + g.kchunk);
+
+  // Per-thread load slots: fixed (row or column, k offset) per slot, so only
+  // the k offset advances between chunks.
+  const double* pa[LA];
+  const double* pb[LB];
+  int ka[LA], kb[LB];
+  bool va[LA], vb[LB];
+#pragma unroll
+  for (int q = 0; q < LA; ++q) {
+    const int idx = tid + NTH * q;
+    int i, kk;
+    if (TA) { kk = idx % BK; i = idx / BK; } else { i = idx % BM; kk = idx / BM; }
+    const long gi = i0 + i;
+    va[q] = gi < M;
+    ka[q] = kk;
+    pa[q] = TA ? g.A + (va[q] ? gi : 0) * g.lda + kbeg + kk : g.A + (va[q] ? gi : 0) + (kbeg + kk) * g.lda;
+  }
+#pragma unroll
+  for (int q = 0; q < LB; ++q) {
+    const int idx = tid + NTH * q;
+    int j, kk;
+    if (TB) { j = idx % BN; kk = idx / BN; } else { kk = idx % BK; j = idx / BK; }
+    const long gj = j0 + j;
+    vb[q] = gj < N;
+    kb[q] = kk;
+    const long cj = vb[q] ? (g.bcol ? g.bcol[gj] : gj) : 0;
+    pb[q] = TB ? g.B + cj + (kbeg + kk) * g.ldb : g.B + cj * g.ldb + kbeg + kk;
+  }
+  const long sa = TA ? BK : (long)BK * g.lda;   // pointer step per chunk
+  const long sbk = TB ? (long)BK * g.ldb : BK;
+
+  acc_t acc[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) acc[a][b] = MF::zero();
+
+  double ra[LA], rb[LB];
+  auto load_tiles = [&](long k0) {
+    const long rem = kend - k0;
+#pragma unroll
+    for (int q = 0; q < LA; ++q) ra[q] = (va[q] && ka[q] < rem) ? *pa[q] : 0.0;
+#pragma unroll
+    for (int q = 0; q < LB; ++q) rb[q] = (vb[q] && kb[q] < rem) ? *pb[q] : 0.0;
+#pragma unroll
+    for (int q = 0; q < LA; ++q) pa[q] += sa;
+#pragma unroll
+    for (int q = 0; q < LB; ++q) pb[q] += sbk;
+  };
+  auto store_tiles = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < LA; ++q) {
+      const int idx = tid + NTH * q;
+      int i, kk;
+      if (TA) { kk = idx % BK; i = idx / BK; } else { i = idx % BM; kk = idx / BM; }
+      sA[buf][kk][i] = cvt<T>(ra[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      const int idx = tid + NTH * q;
+      int j, kk;
+      if (TB) { j = idx % BN; kk = idx / BN; } else { kk = idx % BK; j = idx / BK; }
+      sB[buf][kk][j] = cvt<T>(rb[q]);
+    }
+  };
+
+  if (kbeg < kend) {
+    load_tiles(kbeg);
+    store_tiles(0);
+    __syncthreads();
+    int buf = 0;
+    for (long k0 = kbeg; k0 < kend; k0 += BK) {
+      const bool more = k0 + BK < kend;
+      if (more) load_tiles(k0 + BK);
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += MF::KS) {
+        T af[FM], bf[FN];
+#pragma unroll
+        for (int a = 0; a < FM; ++a) af[a] = sA[buf][kk + (lane >> 4)][wm * WM + a * 16 + (lane & 15)];
+#pragma unroll
+        for (int b = 0; b < FN; ++b) bf[b] = sB[buf][kk + (lane >> 4)][wn * WN + b * 16 + (lane & 15)];
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+          for (int b = 0; b < FN; ++b) acc[a][b] = MF::run(bf[b], af[a], acc[a][b]);
+      }
+      if (more) store_tiles(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+
+  // epilogue: the block computed is C^T, so lane holds C(i = base_i + lane%16,
+  // j = base_j + MF::row(lane, r))
+#pragma unroll
+  for (int a = 0; a < FM; ++a) {
+    const long gi = i0 + wm * WM + a * 16 + (lane & 15);
+#pragma unroll
+    for (int b = 0; b < FN; ++b) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long gj = j0 + wn * WN + b * 16 + MF::row(lane, r);
+        if (gi < M && gj < N) {
+          const double v = (double)acc[a][b][r];
+          if (g.partial) {
+            g.partial[(long)blockIdx.z * M * N + gi + gj * M] = v;
+          } else {
+            double* c = g.C + gi + gj * g.ldc;
+            *c = (g.beta == 0.0) ? g.alpha * v : g.alpha * v + g.beta * (*c);
+          }
+        }
+      }
+    }
+  }
+}
+
+// Named instances: the trailing update's two big products and the sketch get
+// their own kernel symbols so that profiles attribute time to them.
+#define QRCP_GEMM_KERNEL(NAME)                                                              \
+  template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, typename T>                   \
+  __global__ __launch_bounds__(64 * WGM * WGN) void NAME(GemmArgs g) {                        \
+    gemm_body<BM, BN, WGM, WGN, TA, TB, T>(g);                                                \
+  }
+QRCP_GEMM_KERNEL(gemm_kernel)
+QRCP_GEMM_KERNEL(trailing_update_kernel)
+QRCP_GEMM_KERNEL(trailing_w_kernel)
+QRCP_GEMM_KERNEL(sketch_gemm_kernel)
+#undef QRCP_GEMM_KERNEL
+
+// BF16 x BF16 -> FP32 sketch kernel: op(A) = S (from S^T stored K x M, TA),
+// op(B) = the FP64 matrix (K x N).  BK = 32, two k-steps of 16 per chunk.
+__global__ __launch_bounds__(256) void gemm_bf16_tn_kernel(GemmArgs g) {
+  constexpr int BM = 64, BN = 64, BK = 32;
+  constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
+  __shared__ unsigned short sA[BM][BK + 4];
+  __shared__ unsigned short sB[BN][BK + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int i0 = blockIdx.y * BM, j0 = blockIdx.x * BN;
+  const int M = g.M, N = g.N;
+  const long kbeg = (long)blockIdx.z * g.kchunk;
+  const long kend = min((long)g.K, kbeg + g.kchunk);
+  f4v acc[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) acc[a][b] = f4v{0.f, 0.f, 0.f, 0.f};
+  for (long k0 = kbeg; k0 < kend; k0 += BK) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < BM * BK / 256; ++q) {
+      const int idx = tid + 256 * q, kk = idx % BK, i = idx / BK;
+      const long gi = i0 + i, gk = k0 + kk;
+      sA[i][kk] = (gi < M && gk < kend) ? to_bf16_bits(g.A[gk + gi * g.lda]) : (unsigned short)0;
+    }
+#pragma unroll
+    for (int q = 0; q < BN * BK / 256; ++q) {
+      const int idx = tid + 256 * q, kk = idx % BK, j = idx / BK;
+      const long gj = j0 + j, gk = k0 + kk;
+      sB[j][kk] = (gj < N && gk < kend) ? to_bf16_bits(g.B[gk + gj * g.ldb]) : (unsigned short)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      s4v af[FM], bf[FN];
+      const int kq = kk + 4 * (lane >> 4);
+#pragma unroll
+      for (int a = 0; a < FM; ++a) {
+        const unsigned short* p = &sA[wm * WM + a * 16 + (lane & 15)][kq];
+        af[a] = s4v{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
+      }
+#pragma unroll
+      for (int b = 0; b < FN; ++b) {
+        const unsigned short* p = &sB[wn * WN + b * 16 + (lane & 15)][kq];
+        bf[b] = s4v{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
+      }
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bf[b], af[a], acc[a][b], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < FM; ++a) {
+    const long gi = i0 + wm * WM + a * 16 + (lane & 15);
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long gj = j0 + wn * WN + b * 16 + 4 * (lane >> 4) + r;
+        if (gi < M && gj < N) {
+          const double v = (double)acc[a][b][r];
+          if (g.partial) g.partial[(long)blockIdx.z * M * N + gi + gj * M] = v;
+          else g.C[gi + gj * g.ldc] = g.alpha * v;
+        }
+      }
+  }
+}
+
+// Fixed-order reduction of split-K partials: C = alpha * sum_z P_z + beta * C.
+// For the BF16 path (fp32_sum) the partials are summed in FP32 so the whole
+// accumulation stays FP32.
+__global__ void splitk_reduce_kernel(const double* P, int splits, int M, int N, double alpha,
+                                     double beta, double* C, long ldc, int fp32_sum) {
+  const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long MN = (long)M * N;
+  if (idx >= MN) return;
+  const long i = idx % M, j = idx / M;
+  double v;
+  if (fp32_sum) {
+    float s = 0.f;
+    for (int z = 0; z < splits; ++z) s += (float)P[z * MN + idx];
+    v = (double)s;
+  } else {
+    double s = 0.0;
+    for (int z = 0; z < splits; ++z) s += P[z * MN + idx];
+    v = s;
+  }
+  double* c = C + i + j * ldc;
+  *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
+}
+
+__global__ void scale_kernel(double* C, long ldc, int M, int N, double beta) {
+  const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (idx >= (long)M * N) return;
+  double* c = C + idx % M + (idx / M) * ldc;
+  *c = (beta == 0.0) ? 0.0 : beta * (*c);
+}
+
+template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, typename T>
+static void launch_tile(const GemmArgs& g, int splits, hipStream_t st) {
+  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, splits);
+  dim3 block(64 * WGM * WGN);
+  switch (g.kind) {
+    case GemmKind::TrailingUpdate:
+      hipLaunchKernelGGL((trailing_update_kernel<BM, BN, WGM, WGN, TA, TB, T>), grid, block, 0, st, g);
+      break;
+    case GemmKind::TrailingW:
+      hipLaunchKernelGGL((trailing_w_kernel<BM, BN, WGM, WGN, TA, TB, T>), grid, block, 0, st, g);
+      break;
+    case GemmKind::Sketch:
+      hipLaunchKernelGGL((sketch_gemm_kernel<BM, BN, WGM, WGN, TA, TB, T>), grid, block, 0, st, g);
+      break;
+    default:
+      hipLaunchKernelGGL((gemm_kernel<BM, BN, WGM, WGN, TA, TB, T>), grid, block, 0, st, g);
+  }
+}
+
+// Tile configuration: 0 = automatic; 1 = 64x64 (4 waves); 2 = 128x128 (4 waves);
+// 3 = 128x128 (8 waves); 4 = 128x64 (4 waves).  QRCP_GEMM_TILE overrides the
+// automatic choice (used for tuning sweeps).
+static int tile_override() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = getenv("QRCP_GEMM_TILE");
+    v = e ? atoi(e) : 0;
+  }
+  return v;
+}
+
+template <bool TA, bool TB, typename T>
+static void launch_shape(const GemmArgs& g, int splits, hipStream_t st) {
+  int cfg = tile_override();
+  if (cfg == 0) {
+    const long tiles128 = (long)((g.M + 127) / 128) * ((g.N + 127) / 128) * splits;
+    cfg = (g.M >= 128 && g.N >= 128 && tiles128 >= 240) ? 3 : 1;
+  }
+  switch (cfg) {
+    case 2: launch_tile<128, 128, 2, 2, TA, TB, T>(g, splits, st); break;
+    case 3: launch_tile<128, 128, 2, 4, TA, TB, T>(g, splits, st); break;
+    case 4: launch_tile<128, 64, 2, 2, TA, TB, T>(g, splits, st); break;
+    default: launch_tile<64, 64, 2, 2, TA, TB, T>(g, splits, st); break;
+  }
+}
+
+size_t gemm_splitk_bytes(long M, long N, int splits) { return (size_t)M * N * splits * sizeof(double); }
+
+// Chooses a split of K when the output has too few tiles to fill the GPU.
+int gemm_pick_splits(long M, long N, long K) {
+  const long tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  if (tiles >= 256 || K < 512) return 1;
+  long s = (512 + tiles - 1) / tiles;
+  const long kmax = K / 256;  // keep >= 256 per split
+  if (s > kmax) s = kmax;
+  if (s > 64) s = 64;
+  return s < 1 ? 1 : (int)s;
+}
+
+int gemm(bool ta, bool tb, Prec prec, GemmArgs g, double* split_ws, size_t split_ws_bytes,
+         hipStream_t st) {
+  if (g.M <= 0 || g.N <= 0) return QRCP_OK;
+  if (g.K <= 0) {
+    // empty product: C = beta * C
+    if (g.beta == 1.0) return QRCP_OK;
+    hipLaunchKernelGGL(scale_kernel, dim3((g.M * (long)g.N + 255) / 256), dim3(256), 0, st, g.C,
+                       g.ldc, g.M, g.N, g.beta);
+    QRCP_LAUNCHED("gemm scale");
+    return QRCP_OK;
+  }
+  int splits = 1;
+  if (split_ws && !g.bcol) splits = gemm_pick_splits(g.M, g.N, g.K);
+  if (splits > 1 && gemm_splitk_bytes(g.M, g.N, splits) > split_ws_bytes) splits = 1;
+  const long BKc = (prec == Prec::BF16) ? 32 : 16;
+  long chunk = (g.K + splits - 1) / splits;
+  chunk = (chunk + BKc - 1) / BKc * BKc;
+  splits = (int)((g.K + chunk - 1) / chunk);
+  g.kchunk = (int)chunk;
+  const double alpha = g.alpha, beta = g.beta;
+  double* C = g.C;
+  const long ldc = g.ldc;
+  g.partial = (splits > 1) ? split_ws : nullptr;
+  if (prec == Prec::BF16) {
+    if (!ta || tb) return QRCP_ERR_UNSUPPORTED;
+    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, splits);
+    if (splits == 1) g.partial = nullptr;
+    hipLaunchKernelGGL(gemm_bf16_tn_kernel, grid, dim3(256), 0, st, g);
+  } else if (prec == Prec::F32) {
+    if (ta && !tb) launch_shape<true, false, float>(g, splits, st);
+    else if (!ta && !tb) launch_shape<false, false, float>(g, splits, st);
+    else if (!ta && tb) launch_shape<false, true, float>(g, splits, st);
+    else launch_shape<true, true, float>(g, splits, st);
+  } else {
+    if (ta && !tb) launch_shape<true, false, double>(g, splits, st);
+    else if (!ta && !tb) launch_shape<false, false, double>(g, splits, st);
+    else if (!ta && tb) launch_shape<false, true, double>(g, splits, st);
+    else launch_shape<true, true, double>(g, splits, st);
+  }
+  QRCP_LAUNCHED("gemm");
+  if (splits > 1) {
+    const long MN = (long)g.M * g.N;
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((MN + 255) / 256), dim3(256), 0, st, split_ws,
+                       splits, g.M, g.N, alpha, beta, C, ldc, prec != Prec::F64 ? 1 : 0);
+    QRCP_LAUNCHED("splitk_reduce");
+  }
+  return QRCP_OK;
+}
+
+}  // namespace qrcp

@@ -1,0 +1,176 @@
+// Householder factorization of a tall narrow leaf (mi x ib, ib <= 32) for the
+// unpivoted blocked QR baseline (GEQRF semantics, LAPACK DLARFG convention).
+//
+// One cooperative kernel: the mi rows are spread over G workgroups, one row per
+// thread with its ib values in registers.  Column j needs, from all rows below
+// j, the sum of squares of x_j and the dot products of x_j with the later
+// columns; those ib partial sums (plus row j itself, from its owner) are
+// exchanged through sentinel-initialised record slots, one slot per (column,
+// workgroup), exactly as in the pivot-selection kernel.  With
+// v = [1; x/(alpha - beta)] the reflector's action on column c follows from
+// the exchanged sums: v^T a_c = a_c(j) + (x^T a_c)/(alpha - beta).
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace qrcp {
+
+namespace {
+constexpr int IB = 32;
+constexpr int NT = 256;
+constexpr int RWH = 2 * IB;
+constexpr uint64_t SENT = 0xFFF0DEADBEEFCAFEull;
+
+struct LeafArgs {
+  double* A;
+  long lda;
+  long mi;
+  int ib;
+  double* tau;
+  uint64_t* rec;
+  int* status;
+};
+
+__device__ __forceinline__ uint64_t poll_w(uint64_t* p, bool& to) {
+  if (to) return 0;
+  uint64_t v = load_agent(p);
+  long spins = 0;
+  while (v == SENT) {
+    if (++spins > kSpinLimit) { to = true; return 0; }
+    __builtin_amdgcn_s_sleep(1);
+    v = load_agent(p);
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(NT) void hh_leaf_kernel(LeafArgs a) {
+  __shared__ double sRed[NT / 64][64][IB + 1];  // per-wave rows -> reduced per wave below
+  __shared__ double sSum[8][IB];
+  __shared__ double sAll[8][IB];
+  __shared__ double sTot[IB];
+  __shared__ double sRow[IB];
+  __shared__ int sflag;
+  const int g = blockIdx.x, G = gridDim.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const long R = (a.mi + G - 1) / G;
+  const long r = (long)g * R + tid;
+  const bool mine = tid < R && r < a.mi;
+  const int ib = a.ib;
+  double x[IB];
+#pragma unroll
+  for (int c = 0; c < IB; ++c) x[c] = (mine && c < ib) ? a.A[r + (long)c * a.lda] : 0.0;
+  bool to = false;
+  if (tid == 0) sflag = 0;
+  __syncthreads();
+
+#pragma unroll
+  for (int j = 0; j < IB; ++j) {
+    if (j < ib) {
+      // ---- partial sums of my row: slot j = x_j^2, slot c > j = x_j x_c ----
+      const bool below = mine && r > j;
+#pragma unroll
+      for (int c = 0; c < IB; ++c) sRed[wv][lane][c] = (below && c >= j) ? x[j] * x[c] : 0.0;
+      __syncthreads();
+      {
+        // 256 threads: column c = tid % 32, part = tid / 32 (8 parts x 32 rows)
+        const int c = tid % IB, part = tid / IB;
+        double s = 0.0;
+        for (int q = 0; q < 32; ++q) {
+          const int rr = part * 32 + q;
+          s += sRed[rr >> 6][rr & 63][c];
+        }
+        sSum[part][c] = s;
+      }
+      __syncthreads();
+      uint64_t* myrec = a.rec + ((long)j * G + g) * RWH;
+      if (tid < IB) {
+        double s = 0.0;
+        for (int p = 0; p < 8; ++p) s += sSum[p][tid];
+        store_agent(myrec + tid, dbits(s));
+      }
+      if (mine && r == j) {
+#pragma unroll
+        for (int c = 0; c < IB; ++c) store_agent(myrec + IB + c, dbits(x[c]));
+      }
+      // ---- combine all workgroups ----
+      {
+        const int c = tid % IB, part = tid / IB;
+        double s = 0.0;
+        if (c >= j && c < ib)
+          for (int gg = part; gg < G; gg += 8) s += bitsd(poll_w(a.rec + ((long)j * G + gg) * RWH + c, to));
+        sAll[part][c] = s;
+      }
+      const int owner = (int)(j / R);
+      if (tid < IB && tid < ib)
+        sRow[tid] = bitsd(poll_w(a.rec + ((long)j * G + owner) * RWH + IB + tid, to));
+      __syncthreads();
+      if (tid < IB) {
+        double s = 0.0;
+        for (int p = 0; p < 8; ++p) s += sAll[p][tid];
+        sTot[tid] = s;
+      }
+      if (to) sflag = 1;
+      __syncthreads();
+      if (sflag) {
+        if (tid == 0) store_agent_i32(a.status, QRCP_ERR_TIMEOUT);
+        return;
+      }
+      const double alpha = sRow[j], xx = sTot[j];
+      double beta = alpha, tau = 0.0, inv = 1.0;
+      if (xx != 0.0) {
+        const double nrm = sqrt(alpha * alpha + xx);
+        beta = (alpha < 0.0) ? nrm : -nrm;
+        tau = (beta - alpha) / beta;
+        inv = alpha - beta;
+      }
+      if (g == 0 && tid == 0) a.tau[j] = tau;
+      if (mine && r >= j) {
+        const double v = (r == j) ? 1.0 : (xx != 0.0 ? x[j] / inv : 0.0);
+        if (tau != 0.0) {
+#pragma unroll
+          for (int c = 0; c < IB; ++c) {
+            if (c > j && c < ib) {
+              const double w = sRow[c] + sTot[c] / inv;
+              x[c] -= tau * w * v;
+            }
+          }
+        }
+        x[j] = (r == j) ? beta : v;
+      }
+      __syncthreads();
+    }
+  }
+  if (mine) {
+#pragma unroll
+    for (int c = 0; c < IB; ++c)
+      if (c < ib) a.A[r + (long)c * a.lda] = x[c];
+  }
+}
+
+int leaf_groups(long mi) {
+  long G = (mi + NT - 1) / NT;
+  if (G < 1) G = 1;
+  return (int)G;
+}
+
+}  // namespace
+
+size_t hh_leaf_records_bytes(i64 mi) {
+  return (size_t)IB * leaf_groups(mi) * RWH * sizeof(uint64_t);
+}
+
+int launch_hh_leaf(double* A, i64 lda, i64 mi, int ib, double* tau, uint64_t* rec,
+                   size_t rec_bytes, int* status, hipStream_t st) {
+  if (mi <= 0 || ib <= 0) return QRCP_OK;
+  if (ib > IB) return QRCP_ERR_UNSUPPORTED;
+  const int G = leaf_groups(mi);
+  if (G > 256) return QRCP_ERR_UNSUPPORTED;
+  const size_t need = hh_leaf_records_bytes(mi);
+  if (need > rec_bytes) return QRCP_ERR_WORKSPACE;
+  QRCP_TRY(launch_fill_u64(rec, (i64)(need / 8), SENT, st));
+  LeafArgs args{A, (long)lda, (long)mi, ib, tau, rec, status};
+  void* params[] = {&args};
+  QRCP_TRY(launch_resident((const void*)hh_leaf_kernel, dim3(G), dim3(NT), params, 0, st));
+  return QRCP_OK;
+}
+
+}  // namespace qrcp

@@ -1,0 +1,814 @@
+// Host driver of the C ABI (include/qrcp.h): argument checks, workspace
+// layout, the per-block loop of the blocked randomized QRCP and the unpivoted
+// Householder QR baseline.  All device work goes to the caller's stream; the
+// loop reads one small status record back per block (block rank after the
+// Cholesky step, error status), so the host knows the block rank k before it
+// enqueues the k-dependent launches of the block.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "steps.hpp"
+
+namespace qrcp {
+
+size_t hh_leaf_records_bytes(i64 mi);
+int launch_hh_leaf(double* A, i64 lda, i64 mi, int ib, double* tau, uint64_t* rec,
+                   size_t rec_bytes, int* status, hipStream_t st);
+
+static thread_local std::string g_last_error;
+
+int launch_resident(const void* fn, dim3 grid, dim3 block, void** params, size_t smem,
+                    hipStream_t st) {
+  static std::mutex mu;
+  static std::map<std::tuple<const void*, unsigned, size_t, int>, int> cache;
+  int dev = 0;
+  QRCP_HIP(hipGetDevice(&dev));
+  int fit = 0;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto key = std::make_tuple(fn, block.x, smem, dev);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      fit = it->second;
+    } else {
+      int cus = 0, per = 0;
+      QRCP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+      QRCP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, (int)block.x, smem));
+      fit = cus * per;
+      cache[key] = fit;
+    }
+  }
+  if ((int)(grid.x * grid.y * grid.z) > fit) return QRCP_ERR_UNSUPPORTED;
+  QRCP_HIP(hipLaunchKernel(fn, grid, block, params, smem, st));
+  return QRCP_OK;
+}
+
+void note_hip_error(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+}
+
+// ---------------------------------------------------------------------------
+// Optional stage timing with HIP events (qrcp_profile_*).  Mode 1 records only
+// the trailing-update product (the dominant kernel); mode 2 every stage.
+// Events are recorded on the caller's stream, so they time the device work of
+// each stage; the accumulated records are read back by qrcp_profile_read().
+// ---------------------------------------------------------------------------
+enum Stage {
+  kStSketch, kStLu, kStPerm, kStSketchQr, kStCholGram, kStCholQ, kStRecon, kStLarft,
+  kStTrailW, kStTrailUpdate, kStSketchUpdate, kStFinal, kStGeqrfPanel, kNumStages
+};
+static const char* kStageNames[kNumStages] = {
+    "sketch", "lu_pivots", "permute", "sketch_qr", "precondition_gram_potrf", "cholqr_q",
+    "reconstruct_r11", "larft", "trailing_w", "trailing_update", "sketch_update", "finalize",
+    "geqrf_panel"};
+
+struct Profiler {
+  int mode = 0;
+  struct Rec {
+    hipEvent_t a, b;
+    int stage;
+    double flops;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+};
+static Profiler g_prof;
+
+struct ProfScope {
+  int stage;
+  double flops;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  ProfScope(int s, double f, hipStream_t stream) : stage(s), flops(f), st(stream) {
+    if (g_prof.mode == 2 || (g_prof.mode == 1 && s == kStTrailUpdate)) {
+      a = g_prof.get();
+      if (a) hipEventRecord(a, st);
+    }
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = g_prof.get();
+    if (!b) return;
+    hipEventRecord(b, st);
+    g_prof.recs.push_back({a, b, stage, flops});
+  }
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr size_t kSplitBytes = 40u << 20;  // split-K partials (any shape fits, see gemm_pick_splits)
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct FactorWs {
+  double* big;  // max(m d, m n): S^T at the start, final-permutation scratch at the end
+  double *sk0, *sk1, *xw;
+  uint64_t* rec;
+  size_t rec_bytes;
+  i64 *J[2], *phys[2], *inv, *plan, *ipiv, *jsk;
+  double *tmp, *Y;  // m x b each
+  double *G, *Rc, *Rinv, *Tm, *P, *X, *Uinv, *R11inv, *R2, *RcN;
+  double* dsig;
+  double *W, *W2;
+  double *colss, *ref;
+  int *status, *kdev, *info;
+  double* split;
+  void* skqr;
+  size_t skqr_bytes;
+};
+
+size_t carve_factor(char* base, i64 m, i64 n, i64 b, int d, FactorWs* w) {
+  Carver c{base};
+  const i64 bb = std::max<i64>(b, 1);
+  w->big = c.take<double>((size_t)std::max(m * (i64)d, m * n));
+  w->sk0 = c.take<double>((size_t)d * n);
+  w->sk1 = c.take<double>((size_t)d * n);
+  w->xw = c.take<double>((size_t)d * n);
+  w->rec_bytes = lu_records_bytes(d, n);
+  w->rec = c.take<uint64_t>(w->rec_bytes / 8 + 1);
+  for (int i = 0; i < 2; ++i) {
+    w->J[i] = c.take<i64>(n + 1);
+    w->phys[i] = c.take<i64>(n + 1);
+  }
+  w->inv = c.take<i64>(n + 1);
+  w->plan = c.take<i64>(8 + 3 * bb);
+  w->ipiv = c.take<i64>(d + 1);
+  w->jsk = c.take<i64>(n + 1);
+  w->tmp = c.take<double>((size_t)m * bb);
+  w->Y = c.take<double>((size_t)m * bb);
+  double** sq[] = {&w->G, &w->Rc, &w->Rinv, &w->Tm, &w->P, &w->X, &w->Uinv, &w->R11inv, &w->R2, &w->RcN};
+  for (double** p : sq) *p = c.take<double>((size_t)bb * bb);
+  w->dsig = c.take<double>(bb);
+  w->W = c.take<double>((size_t)bb * n);
+  w->W2 = c.take<double>((size_t)bb * n);
+  w->colss = c.take<double>(n + 1);
+  w->ref = c.take<double>(1);
+  w->status = c.take<int>(4);
+  w->kdev = c.take<int>(4);
+  w->info = c.take<int>(4);
+  w->split = c.take<double>(kSplitBytes / 8);
+  w->skqr_bytes = sketch_qr_ws_bytes(d, n);
+  w->skqr = c.take<char>(w->skqr_bytes);
+  return c.off + kAlign;
+}
+
+int sketch_rows(i64 b, double gamma) {
+  return (int)std::ceil(gamma * (double)b - 1e-12);
+}
+
+qrcp_opts defaults() {
+  qrcp_opts o;
+  o.struct_size = sizeof(qrcp_opts);
+  o.cholqr_passes = 1;
+  o.sketch_precision = 0;
+  o.trailing_precision = 0;
+  o.pivot_base = 0;
+  return o;
+}
+
+qrcp_opts read_opts(const qrcp_opts* p) {
+  qrcp_opts o = defaults();
+  if (!p) return o;
+  const int sz = p->struct_size;
+  if (sz >= (int)(offsetof(qrcp_opts, cholqr_passes) + 4)) o.cholqr_passes = p->cholqr_passes;
+  if (sz >= (int)(offsetof(qrcp_opts, sketch_precision) + 4)) o.sketch_precision = p->sketch_precision;
+  if (sz >= (int)(offsetof(qrcp_opts, trailing_precision) + 4)) o.trailing_precision = p->trailing_precision;
+  if (sz >= (int)(offsetof(qrcp_opts, pivot_base) + 4)) o.pivot_base = p->pivot_base;
+  return o;
+}
+
+int read_back(void* host, const void* dev, size_t bytes, hipStream_t st) {
+  QRCP_HIP(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, st));
+  QRCP_HIP(hipStreamSynchronize(st));
+  return QRCP_OK;
+}
+
+int zero_int(int* p, hipStream_t st) { return launch_fill_u64((uint64_t*)p, 1, 0ull, st); }
+
+GemmArgs ga(int M, int N, int K, const double* A, i64 lda, const double* B, i64 ldb, double* C,
+            i64 ldc, double alpha = 1.0, double beta = 0.0) {
+  GemmArgs g;
+  g.M = M; g.N = N; g.K = K; g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+  g.alpha = alpha; g.beta = beta;
+  return g;
+}
+
+// (H_0..H_{k-1})^T C for a clean unit lower trapezoidal Y (mi x k, ldy):
+// T from the UT transform of Y^T Y, then W = Y^T C, W2 = T^T W, C -= Y W2.
+int apply_qt_clean(const double* Y, i64 mi, int k, i64 ldy, const double* tau, double* C, i64 nc,
+                   i64 ldc, Prec prec, double* G, double* T, i64 ldk, double* W, double* W2,
+                   double* split, size_t split_bytes, hipStream_t st) {
+  if (k <= 0 || nc <= 0 || mi <= 0) return QRCP_OK;
+  {
+    ProfScope ps(kStLarft, 2.0 * mi * k * k, st);
+    QRCP_TRY(gemm(true, false, Prec::F64, ga(k, k, (int)mi, Y, ldy, Y, ldy, G, ldk), split, split_bytes, st));
+    QRCP_TRY(launch_ut_tinv(G, ldk, tau, k, st));
+    QRCP_TRY(launch_trinv_upper(G, ldk, k, T, ldk, st));
+    QRCP_TRY(launch_ut_zero_diag(T, ldk, tau, k, st));
+  }
+  {
+    ProfScope ps(kStTrailW, 2.0 * mi * k * nc + 2.0 * k * k * nc, st);
+    GemmArgs w = ga(k, (int)nc, (int)mi, Y, ldy, C, ldc, W, k);
+    w.kind = GemmKind::TrailingW;
+    QRCP_TRY(gemm(true, false, prec, w, split, split_bytes, st));
+    QRCP_TRY(gemm(true, false, prec, ga(k, (int)nc, k, T, ldk, W, k, W2, k), split, split_bytes, st));
+  }
+  {
+    ProfScope ps(kStTrailUpdate, 2.0 * mi * k * nc, st);
+    GemmArgs u = ga((int)mi, (int)nc, k, Y, ldy, W2, k, C, ldc, -1.0, 1.0);
+    u.kind = GemmKind::TrailingUpdate;
+    QRCP_TRY(gemm(false, false, prec, u, nullptr, 0, st));
+  }
+  return QRCP_OK;
+}
+
+}  // namespace
+}  // namespace qrcp
+
+using namespace qrcp;
+
+extern "C" {
+
+const char* qrcp_status_string(int status) {
+  switch (status) {
+    case QRCP_OK: return "success";
+    case QRCP_ERR_WORKSPACE: return "workspace missing or too small";
+    case QRCP_ERR_HIP: return "HIP runtime error";
+    case QRCP_ERR_NONFINITE: return "non-finite value in the input or the sketch";
+    case QRCP_ERR_UNSUPPORTED: return "unsupported shape or option";
+    case QRCP_ERR_TIMEOUT: return "cross-workgroup wait timed out";
+    default: return status < 0 ? "illegal argument" : "unknown status";
+  }
+}
+
+const char* qrcp_last_error(void) { return g_last_error.c_str(); }
+
+size_t qrcp_workspace_size(int64_t m, int64_t n, int64_t block_size, double sketch_factor,
+                           const qrcp_opts* opts) {
+  (void)opts;
+  if (m < 0 || n < 0 || block_size < 1 || !(sketch_factor >= 1.0)) return 0;
+  FactorWs w;
+  const int d = sketch_rows(block_size, sketch_factor);
+  return carve_factor(nullptr, m, n, std::min<i64>(block_size, std::max<i64>(n, 1)), d, &w);
+}
+
+int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size,
+                double sketch_factor, uint64_t seed, double tol, int64_t* jpiv, double* tau,
+                int64_t* rank, const qrcp_opts* opts_in, void* workspace, size_t workspace_bytes,
+                void* stream) {
+  if (m < 0) return -2;
+  if (n < 0) return -3;
+  if (lda < std::max<int64_t>(1, m)) return -4;
+  if (block_size < 1) return -5;
+  if (!(sketch_factor >= 1.0)) return -6;
+  if (!(tol >= 0.0)) return -8;
+  if (!rank) return -11;
+  const qrcp_opts o = read_opts(opts_in);
+  if (o.cholqr_passes != 1 && o.cholqr_passes != 2) return -12;
+  if (o.sketch_precision < 0 || o.sketch_precision > 1) return -12;
+  if (o.trailing_precision < 0 || o.trailing_precision > 1) return -12;
+  if (o.pivot_base != 0 && o.pivot_base != 1) return -12;
+  if (m < n) return QRCP_ERR_UNSUPPORTED;
+  *rank = 0;
+  if (n == 0) return QRCP_OK;
+  if (!A) return -1;
+  if (!jpiv) return -9;
+  if (!tau) return -10;
+  const i64 b = std::min<i64>(block_size, n);
+  const int d = sketch_rows(block_size, sketch_factor);
+  if (d > 1280 || n > 65536) return QRCP_ERR_UNSUPPORTED;
+  FactorWs w;
+  const size_t need = carve_factor(nullptr, m, n, b, d, &w);
+  if (!workspace || workspace_bytes < need) return QRCP_ERR_WORKSPACE;
+  carve_factor((char*)workspace, m, n, b, d, &w);
+  hipStream_t st = (hipStream_t)stream;
+  const Prec tprec = o.trailing_precision ? Prec::F32 : Prec::F64;
+
+  // ---- sketch M^sk = S A (S generated once, stored transposed) ----
+  {
+    ProfScope ps(kStSketch, 2.0 * d * m * n, st);
+    QRCP_TRY(launch_sketch_operator(w.big, m, d, m, seed, st));
+    GemmArgs g = ga(d, (int)n, (int)m, w.big, m, A, lda, w.sk0, d);
+    g.kind = GemmKind::Sketch;
+    QRCP_TRY(gemm(true, false, o.sketch_precision ? Prec::BF16 : Prec::F64, g, w.split, kSplitBytes, st));
+    QRCP_TRY(launch_sketch_ref(w.sk0, d, d, n, w.colss, w.ref, st));
+  }
+  QRCP_TRY(launch_iota(w.J[0], n, st));
+  QRCP_TRY(launch_iota(w.phys[0], n, st));
+  QRCP_TRY(launch_iota(w.inv, n, st));
+  QRCP_TRY(zero_int(w.status, st));
+
+  int cur = 0;
+  i64 ell = 0;
+  int status = QRCP_OK;
+  for (i64 s = 0; s < n; ) {
+    const i64 ni = n - s, mi = m - s;
+    const int kmax = (int)std::min<i64>(b, std::min(ni, mi));
+    const i64 c = s + kmax;
+    double* Ablk = A + s + s * lda;  // panel top-left (rows s.., physical column s)
+    // 1. pivots of the sketch (Alg. 2 GETRF on the transpose)
+    {
+      ProfScope ps(kStLu, 2.0 * ni * d * d, st);
+      QRCP_TRY(launch_lu_pivots(w.sk0 + s * d, d, ni, d, w.xw, w.rec, w.rec_bytes, w.ipiv, w.jsk,
+                                w.status, st));
+    }
+    // 2. logical maps and the placement plan; 3. permuted sketch
+    {
+      ProfScope ps(kStPerm, 0.0, st);
+      QRCP_TRY(launch_perm_plan(w.jsk, s, n, kmax, w.J[cur], w.J[1 - cur], w.phys[cur],
+                                w.phys[1 - cur], w.inv, w.plan, st));
+      QRCP_TRY(launch_sketch_permute(w.sk0 + s * d, w.sk1 + s * d, d, d, ni, w.jsk, st));
+    }
+    cur = 1 - cur;
+    // 4. R factor of the permuted sketch (back into sk0, logical positions)
+    {
+      ProfScope ps(kStSketchQr, 2.0 * d * d * ni, st);
+      QRCP_TRY(run_sketch_qr(w.sk1 + s * d, d, ni, d, w.sk0 + s * d, d, w.skqr, w.skqr_bytes,
+                             w.status, st));
+    }
+    const double* Rsk = w.sk0 + s * d;
+    // 5. tri_rank
+    QRCP_TRY(launch_trirank(Rsk, d, kmax, tol, w.ref, w.kdev, st));
+    // 6. place the panel columns (all m rows)
+    {
+      ProfScope ps(kStPerm, 0.0, st);
+      QRCP_TRY(launch_place_columns(A, lda, m, s, kmax, w.plan, w.tmp, m, st));
+    }
+    {
+      ProfScope ps(kStCholGram, 4.0 * mi * kmax * kmax, st);
+      // 7. precondition with the leading k x k block of Rsk (k on the device)
+      QRCP_TRY(launch_trinv_upper(Rsk, d, kmax, w.Rinv, b, st));
+      QRCP_TRY(launch_mask_k(w.Rinv, b, kmax, w.kdev, st));
+      QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, kmax, kmax, Ablk, lda, w.Rinv, b, w.Y, m),
+                    nullptr, 0, st));
+      // 8. Gram and Cholesky; a breakdown (or the rank cut) ends the factor at info
+      QRCP_TRY(gemm(true, false, Prec::F64, ga(kmax, kmax, (int)mi, w.Y, m, w.Y, m, w.G, b), w.split,
+                    kSplitBytes, st));
+      QRCP_TRY(launch_potrf_upper(w.G, b, kmax, w.info, st));
+    }
+    int hs[3];
+    QRCP_HIP(hipMemcpyAsync(hs, w.status, sizeof(int), hipMemcpyDeviceToHost, st));
+    QRCP_TRY(read_back(hs + 1, w.info, sizeof(int), st));
+    if (hs[0] != QRCP_OK) { status = hs[0]; ell = s; break; }
+    int k = hs[1];
+    if (k == 0) { ell = s; break; }
+    // Q = M^pre Rc^{-1}
+    {
+    ProfScope psq(kStCholQ, 2.0 * mi * k * k, st);
+    QRCP_TRY(launch_trinv_upper(w.G, b, k, w.Rinv, b, st));
+    if (o.cholqr_passes == 2) {
+      QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, k, k, w.Y, m, w.Rinv, b, w.tmp, m), nullptr, 0, st));
+      QRCP_TRY(gemm(true, false, Prec::F64, ga(k, k, (int)mi, w.tmp, m, w.tmp, m, w.R2, b), w.split, kSplitBytes, st));
+      QRCP_TRY(launch_potrf_upper(w.R2, b, k, w.info, st));
+      QRCP_TRY(read_back(hs + 2, w.info, sizeof(int), st));
+      if (hs[2] < k) {
+        // second pass broke down: keep the columns factored by both passes
+        k = hs[2];
+        if (k == 0) { ell = s; break; }
+        QRCP_TRY(launch_trinv_upper(w.G, b, k, w.Rinv, b, st));
+        QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, k, k, w.Y, m, w.Rinv, b, w.tmp, m), nullptr, 0, st));
+      }
+      QRCP_TRY(launch_trinv_upper(w.R2, b, k, w.Uinv, b, st));
+      QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, k, k, w.tmp, m, w.Uinv, b, Ablk, lda), nullptr, 0, st));
+      // Rc <- R2 Rc
+      QRCP_TRY(gemm(false, false, Prec::F64, ga(k, k, k, w.R2, b, w.G, b, w.RcN, b), nullptr, 0, st));
+      QRCP_TRY(launch_copy2d(w.RcN, b, w.G, b, k, k, st));
+    } else {
+      QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, k, k, w.Y, m, w.Rinv, b, Ablk, lda), nullptr, 0, st));
+    }
+    }
+    // 9. Householder reconstruction: sign-modified LU of the head, Y2 = Q2 U^{-1}
+    {
+    ProfScope psr(kStRecon, 2.0 * (mi - k) * k * k + 2.0 * k * k * k, st);
+    QRCP_TRY(launch_headlu(Ablk, lda, k, w.dsig, st));
+    QRCP_TRY(launch_tau_from_u(Ablk, lda, k, w.dsig, tau + s, st));
+    QRCP_TRY(launch_trinv_upper(Ablk, lda, k, w.Uinv, b, st));
+    if (mi > k) {
+      QRCP_TRY(gemm(false, false, Prec::F64, ga((int)(mi - k), k, k, Ablk + k, lda, w.Uinv, b, w.Y + k, m),
+                    nullptr, 0, st));
+      QRCP_TRY(launch_copy2d(w.Y + k, m, Ablk + k, lda, mi - k, k, st));
+    }
+    QRCP_TRY(launch_unit_lower(Ablk, lda, k, w.Y, m, st));
+    //    R11 = diag(D) Rc Rsk(0:k, 0:k)
+    QRCP_TRY(gemm(false, false, Prec::F64, ga(k, k, k, w.G, b, Rsk, d, w.P, b), nullptr, 0, st));
+    QRCP_TRY(launch_write_r11(w.P, b, k, w.dsig, Ablk, lda, st));
+    }
+    // 10-11. trailing update of the physical columns s+k .. n-1 (rows s..m-1)
+    const i64 nc = n - s - k;
+    QRCP_TRY(apply_qt_clean(w.Y, mi, k, m, tau + s, A + s + (s + k) * lda, nc, lda, tprec, w.Tm,
+                            w.R11inv, b, w.W, w.W2, w.split, kSplitBytes, st));
+    if (k < kmax || c >= n) { ell = s + k; break; }
+    // 12. sketch update: M^sk(0:b, c:) = Rsk12 - Rsk11 R11^{-1} R12 (R12 read through the map)
+    ProfScope psu(kStSketchUpdate, 2.0 * b * b * (n - c), st);
+    QRCP_TRY(launch_trinv_upper(Ablk, lda, (int)b, w.R11inv, b, st));
+    QRCP_TRY(gemm(false, false, Prec::F64, ga((int)b, (int)b, (int)b, Rsk, d, w.R11inv, b, w.X, b), nullptr, 0, st));
+    {
+      GemmArgs g = ga((int)b, (int)(n - c), (int)b, w.X, b, A + s, lda, w.sk0 + c * d, d, -1.0, 1.0);
+      g.bcol = w.phys[cur] + c;
+      QRCP_TRY(gemm(false, false, Prec::F64, g, nullptr, 0, st));
+    }
+    s = c;
+    ell = s;
+  }
+  if (status == QRCP_OK && ell < std::min(m, n)) {
+    QRCP_TRY(launch_fill(tau + ell, 1, std::min(m, n) - ell, 1, 0.0, st));
+  }
+  if (status == QRCP_OK && ell < n) {
+    QRCP_TRY(launch_final_permute(A, lda, m, ell, n, w.phys[cur], w.big, st));
+  }
+  QRCP_TRY(launch_jpiv_out(w.J[cur], n, o.pivot_base, jpiv, st));
+  QRCP_HIP(hipStreamSynchronize(st));
+  *rank = ell;
+  return status;
+}
+
+// ----------------------------------------------------------------------------
+// Unpivoted blocked Householder QR (GEQRF storage).
+// ----------------------------------------------------------------------------
+static size_t carve_geqrf(char* base, i64 m, i64 n, i64 nb, double** Yc, double** G, double** T,
+                          double** W, double** W2, uint64_t** rec, size_t* rec_bytes, int** status,
+                          double** split) {
+  Carver c{base};
+  *Yc = c.take<double>((size_t)m * nb);
+  *G = c.take<double>((size_t)nb * nb);
+  *T = c.take<double>((size_t)nb * nb);
+  *W = c.take<double>((size_t)nb * n);
+  *W2 = c.take<double>((size_t)nb * n);
+  *rec_bytes = hh_leaf_records_bytes(m);
+  *rec = c.take<uint64_t>(*rec_bytes / 8 + 1);
+  *status = c.take<int>(4);
+  *split = c.take<double>(kSplitBytes / 8);
+  return c.off + kAlign;
+}
+
+size_t qrcp_geqrf_workspace_size(int64_t m, int64_t n, int64_t nb) {
+  if (m < 0 || n < 0 || nb < 1) return 0;
+  double *a, *b, *c, *d, *e, *f;
+  uint64_t* r;
+  size_t rb;
+  int* s;
+  return carve_geqrf(nullptr, m, n, std::min<i64>(nb, std::max<i64>(n, 1)), &a, &b, &c, &d, &e, &r, &rb, &s, &f);
+}
+
+int qrcp_geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, int64_t nb,
+               void* workspace, size_t workspace_bytes, void* stream) {
+  if (m < 0) return -2;
+  if (n < 0) return -3;
+  if (lda < std::max<int64_t>(1, m)) return -4;
+  if (nb < 1) return -6;
+  if (m < n) return QRCP_ERR_UNSUPPORTED;
+  if (n == 0) return QRCP_OK;
+  if (!A) return -1;
+  if (!tau) return -5;
+  if (m > 65536) return QRCP_ERR_UNSUPPORTED;
+  nb = std::min<i64>(nb, n);
+  double *Yc, *G, *T, *W, *W2, *split;
+  uint64_t* rec;
+  size_t rec_bytes;
+  int* status;
+  const size_t need = carve_geqrf(nullptr, m, n, nb, &Yc, &G, &T, &W, &W2, &rec, &rec_bytes, &status, &split);
+  if (!workspace || workspace_bytes < need) return QRCP_ERR_WORKSPACE;
+  carve_geqrf((char*)workspace, m, n, nb, &Yc, &G, &T, &W, &W2, &rec, &rec_bytes, &status, &split);
+  hipStream_t st = (hipStream_t)stream;
+  QRCP_TRY(zero_int(status, st));
+  constexpr int IB = 32;
+  for (i64 s = 0; s < n; s += nb) {
+    const i64 kb = std::min<i64>(nb, n - s), mi = m - s;
+    double* Ap = A + s + s * lda;
+    for (i64 s2 = 0; s2 < kb; s2 += IB) {
+      const int ib = (int)std::min<i64>(IB, kb - s2);
+      double* Al = Ap + s2 + s2 * lda;
+      QRCP_TRY(launch_hh_leaf(Al, lda, mi - s2, ib, tau + s + s2, rec, rec_bytes, status, st));
+      if (s2 + ib < kb) {
+        // clean copy of the leaf's reflectors, then update the rest of the panel
+        QRCP_TRY(launch_copy2d(Al, lda, Yc, m, mi - s2, ib, st));
+        QRCP_TRY(launch_unit_lower(Al, lda, ib, Yc, m, st));
+        QRCP_TRY(apply_qt_clean(Yc, mi - s2, ib, m, tau + s + s2, Al + ib * lda, kb - s2 - ib, lda,
+                                Prec::F64, G, T, nb, W, W2, split, kSplitBytes, st));
+      }
+    }
+    if (s + kb < n) {
+      QRCP_TRY(launch_copy2d(Ap, lda, Yc, m, mi, kb, st));
+      QRCP_TRY(launch_unit_lower(Ap, lda, (int)kb, Yc, m, st));
+      QRCP_TRY(apply_qt_clean(Yc, mi, (int)kb, m, tau + s, Ap + kb * lda, n - s - kb, lda, Prec::F64,
+                              G, T, nb, W, W2, split, kSplitBytes, st));
+    }
+  }
+  int hs = 0;
+  QRCP_TRY(read_back(&hs, status, sizeof(int), st));
+  return hs;
+}
+
+// ----------------------------------------------------------------------------
+// Step entry points
+// ----------------------------------------------------------------------------
+int qrcp_sketch_operator(double* St, int64_t m, int64_t d, int64_t ldst, uint64_t seed,
+                         void* stream) {
+  if (!St && m * d > 0) return -1;
+  if (m < 0) return -2;
+  if (d < 0) return -3;
+  if (ldst < std::max<int64_t>(1, m)) return -4;
+  QRCP_TRY(launch_sketch_operator(St, m, (int)d, ldst, seed, (hipStream_t)stream));
+  QRCP_HIP(hipStreamSynchronize((hipStream_t)stream));
+  return QRCP_OK;
+}
+
+int qrcp_philox(const uint32_t* ctr, int64_t count, uint32_t key0, uint32_t key1, uint32_t* out,
+                void* stream) {
+  if (count < 0) return -2;
+  QRCP_TRY(launch_philox(ctr, count, key0, key1, out, (hipStream_t)stream));
+  QRCP_HIP(hipStreamSynchronize((hipStream_t)stream));
+  return QRCP_OK;
+}
+
+int qrcp_sketch(const double* A, int64_t m, int64_t n, int64_t lda, int64_t d, uint64_t seed,
+                int32_t precision, double* Msk, int64_t ldmsk, void* workspace,
+                size_t workspace_bytes, void* stream) {
+  if (m < 0) return -2;
+  if (n < 0) return -3;
+  if (lda < std::max<int64_t>(1, m)) return -4;
+  if (d < 1) return -5;
+  if (precision != 0 && precision != 1) return -7;
+  if (ldmsk < d) return -9;
+  const size_t need = (size_t)m * d * 8 + kSplitBytes + 2 * kAlign;
+  if (!workspace || workspace_bytes < need) return QRCP_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  Carver c{(char*)workspace};
+  double* St = c.take<double>((size_t)m * d);
+  double* split = c.take<double>(kSplitBytes / 8);
+  QRCP_TRY(launch_sketch_operator(St, m, (int)d, m, seed, st));
+  QRCP_TRY(gemm(true, false, precision ? Prec::BF16 : Prec::F64,
+                ga((int)d, (int)n, (int)m, St, m, A, lda, Msk, ldmsk), split, kSplitBytes, st));
+  QRCP_HIP(hipStreamSynchronize(st));
+  return QRCP_OK;
+}
+
+size_t qrcp_lu_workspace_size(int64_t d, int64_t ni) {
+  if (d < 1 || ni < 0) return 0;
+  return (size_t)d * ni * 8 + lu_records_bytes((int)d, ni) + 4 * kAlign + 64;
+}
+
+int qrcp_lu_pivots(const double* Msk, int64_t d, int64_t ni, int64_t ldmsk, int64_t* ipiv,
+                   int64_t* jsk, void* workspace, size_t workspace_bytes, void* stream) {
+  if (d < 1) return -2;
+  if (ni < 0) return -3;
+  if (ldmsk < d) return -4;
+  if (ni == 0) return QRCP_OK;
+  if (ni > 65536) return QRCP_ERR_UNSUPPORTED;
+  if (!workspace || workspace_bytes < qrcp_lu_workspace_size(d, ni)) return QRCP_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  Carver c{(char*)workspace};
+  double* xw = c.take<double>((size_t)d * ni);
+  const size_t rb = lu_records_bytes((int)d, ni);
+  uint64_t* rec = c.take<uint64_t>(rb / 8);
+  int* status = c.take<int>(4);
+  QRCP_TRY(zero_int(status, st));
+  QRCP_TRY(launch_lu_pivots(Msk, (int)d, ni, ldmsk, xw, rec, rb, ipiv, jsk, status, st));
+  int hs = 0;
+  QRCP_TRY(read_back(&hs, status, sizeof(int), st));
+  return hs;
+}
+
+size_t qrcp_sketch_qr_workspace_size(int64_t d, int64_t ni) {
+  if (d < 1 || ni < 0) return 0;
+  return sketch_qr_ws_bytes((int)d, ni) + 2 * kAlign + 64;
+}
+
+int qrcp_sketch_qr(const double* B, int64_t d, int64_t ni, int64_t ldb, double* R, int64_t ldr,
+                   void* workspace, size_t workspace_bytes, void* stream) {
+  if (d < 1) return -2;
+  if (ni < 0) return -3;
+  if (ldb < d) return -4;
+  if (ldr < d) return -6;
+  if (ni == 0) return QRCP_OK;
+  if (!workspace || workspace_bytes < qrcp_sketch_qr_workspace_size(d, ni)) return QRCP_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  Carver c{(char*)workspace};
+  int* status = c.take<int>(4);
+  void* ws = c.take<char>(sketch_qr_ws_bytes((int)d, ni));
+  QRCP_TRY(zero_int(status, st));
+  QRCP_TRY(run_sketch_qr(B, (int)d, ni, ldb, R, ldr, ws, sketch_qr_ws_bytes((int)d, ni), status, st));
+  int hs = 0;
+  QRCP_TRY(read_back(&hs, status, sizeof(int), st));
+  return hs;
+}
+
+size_t qrcp_panel_workspace_size(int64_t mi, int64_t k) {
+  if (mi < 0 || k < 0) return 0;
+  const size_t kk = (size_t)std::max<int64_t>(k, 1);
+  return (size_t)mi * kk * 8 * 2 + 6 * kk * kk * 8 + kk * 8 + kSplitBytes + 16 * kAlign;
+}
+
+int qrcp_cholqr(double* P, int64_t mi, int64_t k, int64_t ldp, const double* Rs, int64_t ldrs,
+                double* Rc, int64_t ldrc, int32_t passes, int64_t* keff, void* workspace,
+                size_t workspace_bytes, void* stream) {
+  if (mi < 0) return -2;
+  if (k < 0 || k > mi) return -3;
+  if (ldp < std::max<int64_t>(1, mi)) return -4;
+  if (ldrs < std::max<int64_t>(1, k)) return -6;
+  if (ldrc < std::max<int64_t>(1, k)) return -8;
+  if (passes != 1 && passes != 2) return -9;
+  if (!keff) return -10;
+  *keff = 0;
+  if (k == 0) return QRCP_OK;
+  if (k > 1024) return QRCP_ERR_UNSUPPORTED;
+  if (!workspace || workspace_bytes < qrcp_panel_workspace_size(mi, k)) return QRCP_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  Carver c{(char*)workspace};
+  double* Mp = c.take<double>((size_t)mi * k);
+  double* Q1 = c.take<double>((size_t)mi * k);
+  double* Rinv = c.take<double>((size_t)k * k);
+  double* G = c.take<double>((size_t)k * k);
+  double* G2 = c.take<double>((size_t)k * k);
+  double* Rn = c.take<double>((size_t)k * k);
+  int* info = c.take<int>(4);
+  double* split = c.take<double>(kSplitBytes / 8);
+  const int kk = (int)k;
+  QRCP_TRY(launch_trinv_upper(Rs, ldrs, kk, Rinv, k, st));
+  QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, kk, kk, P, ldp, Rinv, k, Mp, mi), nullptr, 0, st));
+  QRCP_TRY(gemm(true, false, Prec::F64, ga(kk, kk, (int)mi, Mp, mi, Mp, mi, G, k), split, kSplitBytes, st));
+  QRCP_TRY(launch_potrf_upper(G, k, kk, info, st));
+  int t = 0;
+  QRCP_TRY(read_back(&t, info, sizeof(int), st));
+  if (t < kk) {
+    *keff = t;
+    QRCP_TRY(launch_copy2d(G, k, Rc, ldrc, t, t, st));
+    QRCP_HIP(hipStreamSynchronize(st));
+    return QRCP_OK;
+  }
+  QRCP_TRY(launch_trinv_upper(G, k, kk, Rinv, k, st));
+  if (passes == 2) {
+    QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, kk, kk, Mp, mi, Rinv, k, Q1, mi), nullptr, 0, st));
+    QRCP_TRY(gemm(true, false, Prec::F64, ga(kk, kk, (int)mi, Q1, mi, Q1, mi, G2, k), split, kSplitBytes, st));
+    QRCP_TRY(launch_potrf_upper(G2, k, kk, info, st));
+    QRCP_TRY(read_back(&t, info, sizeof(int), st));
+    if (t < kk) {
+      *keff = t;
+      QRCP_TRY(launch_copy2d(G, k, Rc, ldrc, t, t, st));
+      QRCP_HIP(hipStreamSynchronize(st));
+      return QRCP_OK;
+    }
+    QRCP_TRY(launch_trinv_upper(G2, k, kk, Rinv, k, st));
+    QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, kk, kk, Q1, mi, Rinv, k, P, ldp), nullptr, 0, st));
+    QRCP_TRY(gemm(false, false, Prec::F64, ga(kk, kk, kk, G2, k, G, k, Rn, k), nullptr, 0, st));
+    QRCP_TRY(launch_copy2d(Rn, k, Rc, ldrc, k, k, st));
+  } else {
+    QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, kk, kk, Mp, mi, Rinv, k, P, ldp), nullptr, 0, st));
+    QRCP_TRY(launch_copy2d(G, k, Rc, ldrc, k, k, st));
+  }
+  *keff = k;
+  QRCP_HIP(hipStreamSynchronize(st));
+  return QRCP_OK;
+}
+
+int qrcp_reconstruct(double* Q, int64_t mi, int64_t k, int64_t ldq, double* tau, double* dsig,
+                     void* workspace, size_t workspace_bytes, void* stream) {
+  if (mi < 0) return -2;
+  if (k < 0 || k > mi) return -3;
+  if (ldq < std::max<int64_t>(1, mi)) return -4;
+  if (k == 0) return QRCP_OK;
+  if (k > 1024) return QRCP_ERR_UNSUPPORTED;
+  if (!workspace || workspace_bytes < qrcp_panel_workspace_size(mi, k)) return QRCP_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  Carver c{(char*)workspace};
+  double* Yt = c.take<double>((size_t)mi * k);
+  double* Uinv = c.take<double>((size_t)k * k);
+  const int kk = (int)k;
+  QRCP_TRY(launch_headlu(Q, ldq, kk, dsig, st));
+  QRCP_TRY(launch_tau_from_u(Q, ldq, kk, dsig, tau, st));
+  QRCP_TRY(launch_trinv_upper(Q, ldq, kk, Uinv, k, st));
+  if (mi > k) {
+    QRCP_TRY(gemm(false, false, Prec::F64, ga((int)(mi - k), kk, kk, Q + k, ldq, Uinv, k, Yt, mi), nullptr, 0, st));
+    QRCP_TRY(launch_copy2d(Yt, mi, Q + k, ldq, mi - k, k, st));
+  }
+  QRCP_HIP(hipStreamSynchronize(st));
+  return QRCP_OK;
+}
+
+size_t qrcp_apply_qt_workspace_size(int64_t mi, int64_t k, int64_t nc) {
+  if (mi < 0 || k < 0 || nc < 0) return 0;
+  const size_t kk = (size_t)std::max<int64_t>(k, 1);
+  return (size_t)mi * kk * 8 + 2 * kk * kk * 8 + 2 * kk * (size_t)std::max<int64_t>(nc, 1) * 8 +
+         kSplitBytes + 10 * kAlign;
+}
+
+int qrcp_apply_qt(const double* Y, int64_t mi, int64_t k, int64_t ldy, const double* tau,
+                  double* C, int64_t nc, int64_t ldc, int32_t precision, void* workspace,
+                  size_t workspace_bytes, void* stream) {
+  if (mi < 0) return -2;
+  if (k < 0 || k > mi) return -3;
+  if (ldy < std::max<int64_t>(1, mi)) return -4;
+  if (nc < 0) return -7;
+  if (ldc < std::max<int64_t>(1, mi)) return -8;
+  if (precision != 0 && precision != 1) return -9;
+  if (k == 0 || nc == 0) return QRCP_OK;
+  if (k > 1024) return QRCP_ERR_UNSUPPORTED;
+  if (!workspace || workspace_bytes < qrcp_apply_qt_workspace_size(mi, k, nc)) return QRCP_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  Carver c{(char*)workspace};
+  double* Yc = c.take<double>((size_t)mi * k);
+  double* G = c.take<double>((size_t)k * k);
+  double* T = c.take<double>((size_t)k * k);
+  double* W = c.take<double>((size_t)k * nc);
+  double* W2 = c.take<double>((size_t)k * nc);
+  double* split = c.take<double>(kSplitBytes / 8);
+  QRCP_TRY(launch_copy2d(Y, ldy, Yc, mi, mi, k, st));
+  QRCP_TRY(launch_unit_lower(Y, ldy, (int)k, Yc, mi, st));
+  QRCP_TRY(apply_qt_clean(Yc, mi, (int)k, mi, tau, C, nc, ldc, precision ? Prec::F32 : Prec::F64, G,
+                          T, k, W, W2, split, kSplitBytes, st));
+  QRCP_HIP(hipStreamSynchronize(st));
+  return QRCP_OK;
+}
+
+int qrcp_sketch_update(double* Rsk, int64_t d, int64_t b, int64_t nt, int64_t ldrsk,
+                       const double* R11, int64_t ldr11, const double* R12, int64_t ldr12,
+                       void* workspace, size_t workspace_bytes, void* stream) {
+  if (d < 1) return -2;
+  if (b < 1 || b > d) return -3;
+  if (nt < 0) return -4;
+  if (ldrsk < d) return -5;
+  if (ldr11 < b) return -7;
+  if (ldr12 < b) return -9;
+  if (nt == 0) return QRCP_OK;
+  if (b > 1024) return QRCP_ERR_UNSUPPORTED;
+  const size_t need = 2 * (size_t)b * b * 8 + 4 * kAlign;
+  if (!workspace || workspace_bytes < need) return QRCP_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  Carver c{(char*)workspace};
+  double* Rinv = c.take<double>((size_t)b * b);
+  double* X = c.take<double>((size_t)b * b);
+  const int bb = (int)b;
+  QRCP_TRY(launch_trinv_upper(R11, ldr11, bb, Rinv, b, st));
+  QRCP_TRY(gemm(false, false, Prec::F64, ga(bb, bb, bb, Rsk, ldrsk, Rinv, b, X, b), nullptr, 0, st));
+  QRCP_TRY(gemm(false, false, Prec::F64,
+                ga(bb, (int)nt, bb, X, b, R12, ldr12, Rsk + b * ldrsk, ldrsk, -1.0, 1.0), nullptr, 0, st));
+  QRCP_HIP(hipStreamSynchronize(st));
+  return QRCP_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Stage timing
+// ----------------------------------------------------------------------------
+int qrcp_profile_enable(int32_t mode) {
+  if (mode < 0 || mode > 2) return -1;
+  g_prof.mode = mode;
+  g_prof.recs.clear();
+  g_prof.used = 0;
+  return QRCP_OK;
+}
+
+int32_t qrcp_profile_num_stages(void) { return kNumStages; }
+
+const char* qrcp_profile_stage_name(int32_t stage) {
+  return (stage >= 0 && stage < kNumStages) ? kStageNames[stage] : "";
+}
+
+int qrcp_profile_read(int32_t stage, double* ms, int64_t* count, double* flops) {
+  if (stage < 0 || stage >= kNumStages) return -1;
+  double t = 0.0, f = 0.0;
+  int64_t c = 0;
+  for (auto& r : g_prof.recs) {
+    if (r.stage != stage) continue;
+    QRCP_HIP(hipEventSynchronize(r.b));
+    float e = 0.f;
+    QRCP_HIP(hipEventElapsedTime(&e, r.a, r.b));
+    t += e;
+    f += r.flops;
+    ++c;
+  }
+  if (ms) *ms = t;
+  if (count) *count = c;
+  if (flops) *flops = f;
+  return QRCP_OK;
+}
+
+}  // extern "C"

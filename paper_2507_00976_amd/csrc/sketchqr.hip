@@ -1,0 +1,378 @@
+// Householder QR of the permuted wide sketch (Alg. 2 last step, GEQRF with the
+// LAPACK DLARFG sign convention).
+//
+// Head (the first dh = min(d, ni) columns, the only sequential part): one
+// cooperative kernel, workgroup w owning head columns [w PW, (w+1) PW) in LDS.
+// Workgroup p factors its columns once the reflectors of panels 0..p-1 have
+// been applied to them, publishes its reflectors V_p and their compact-WY
+// factor T_p, and raises flag p; workgroups w > p wait for the flag and apply
+// (I - V_p T_p V_p^T)^T to their own columns.  The panel factorization itself
+// is a column-by-column DLARFG + rank-1 update inside LDS.
+//
+// Tail (the remaining ni - dh columns): R_tail = Q^T B_tail with the explicit
+// d x d Q = I - V T V^T, T from the UT transform of V^T V, all on the GEMM
+// kernels.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace qrcp {
+
+int launch_ut_zero_diag(double* T, i64 ldt, const double* tau, int n, hipStream_t st);
+int launch_set_identity(double* dst, i64 ld, i64 n, hipStream_t st);
+
+namespace {
+constexpr int NT = 256;
+constexpr int VCH = 64;  // rows of V_p staged per pass when applying
+
+struct HeadArgs {
+  const double* B;
+  long ldb;
+  int d, dh, pw;
+  double* R;
+  long ldr;
+  double* V;      // d x dh, clean unit lower trapezoidal
+  double* tau;    // dh
+  double* T;      // npanels x pw x pw
+  int* flags;     // npanels, zero on entry
+  int* status;
+};
+
+typedef double hv4 __attribute__((ext_vector_type(4)));
+
+// W(32 x 32) = V_p^T C over rows [p0, d): V_p staged from global in row chunks,
+// C in LDS.  Wave w owns the 16 x 16 block (w & 1, w >> 1) of W; FP64 MFMA.
+// Then C -= V_p W' with W' = T_p^T W.  PW = 32 only (the MFMA path).
+__device__ void apply_panel_mfma(double* sC, int d, const double* V, int p0, int pc, const double* Tg,
+                                 double* sV, double* sW, double* sT, double* sW2) {
+  constexpr int PW = 32;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int e = tid; e < PW * PW; e += NT) sT[e] = Tg[e];
+  hv4 acc = {0.0, 0.0, 0.0, 0.0};
+  const int bi = w & 1, bj = w >> 1;
+  for (int r0 = p0; r0 < d; r0 += VCH) {
+    const int rows = min(VCH, d - r0);
+    __syncthreads();
+    for (int e = tid; e < VCH * PW; e += NT) {
+      const int rr = e % VCH, aa = e / VCH;
+      sV[aa * VCH + rr] = (rr < rows && aa < pc) ? V[(r0 + rr) + (long)(p0 + aa) * d] : 0.0;
+    }
+    __syncthreads();
+    for (int k0 = 0; k0 < rows; k0 += 4) {
+      const int kr = k0 + (lane >> 4);
+      // src0 = A(i, k) = V(r0 + k, 16 bi + i); src1 = B(k, j) = C(r0 + k, 16 bj + j)
+      const double a = (kr < rows) ? sV[(16 * bi + (lane & 15)) * VCH + kr] : 0.0;
+      const double b = (kr < rows) ? sC[(16 * bj + (lane & 15)) * d + r0 + kr] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+  }
+  // D(i, j): lane l, reg r -> i = 4 r + l/16, j = l % 16
+#pragma unroll
+  for (int r = 0; r < 4; ++r) sW[(16 * bi + 4 * r + (lane >> 4)) * PW + 16 * bj + (lane & 15)] = acc[r];
+  __syncthreads();
+  // W' = T^T W (T upper): W'(a, c) = sum_{t <= a} T(t, a) W(t, c)
+  for (int e = tid; e < PW * PW; e += NT) {
+    const int aa = e / PW, c = e % PW;
+    double s = 0.0;
+    for (int t = 0; t <= aa; ++t) s += sT[t + aa * PW] * sW[t * PW + c];
+    sW2[aa * PW + c] = s;
+  }
+  // C -= V W' over row chunks; 16 x 16 output blocks spread over the waves
+  for (int r0 = p0; r0 < d; r0 += VCH) {
+    const int rows = min(VCH, d - r0);
+    __syncthreads();
+    for (int e = tid; e < VCH * PW; e += NT) {
+      const int rr = e % VCH, aa = e / VCH;
+      sV[aa * VCH + rr] = (rr < rows && aa < pc) ? V[(r0 + rr) + (long)(p0 + aa) * d] : 0.0;
+    }
+    __syncthreads();
+    const int nrb = (rows + 15) / 16;
+    for (int blk = w; blk < nrb * 2; blk += NT / 64) {
+      const int rb = blk >> 1, cb = blk & 1;
+      hv4 c4 = {0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < PW; k0 += 4) {
+        const int kr = k0 + (lane >> 4);
+        // src0 = A(i, k) = V(r0 + 16 rb + i, k), src1 = B(k, j) = W'(k, 16 cb + j)
+        const double a = sV[kr * VCH + 16 * rb + (lane & 15)];
+        const double b = sW2[kr * PW + 16 * cb + (lane & 15)];
+        c4 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c4, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * rb + 4 * r + (lane >> 4), j = 16 * cb + (lane & 15);
+        if (i < rows) sC[j * d + r0 + i] -= c4[r];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int PW>
+__global__ __launch_bounds__(NT) void sketch_head_kernel(HeadArgs a) {
+  extern __shared__ double smem[];
+  const int d = a.d, dh = a.dh;
+  double* sC = smem;                       // PW columns x d rows
+  double* sV = sC + (long)PW * d;          // VCH x PW staging
+  double* sW = sV + VCH * PW;              // PW x PW
+  double* sT = sW + PW * PW;               // PW x PW
+  double* sPart = sT + PW * PW;            // max(PW x PW, NT) scratch
+  __shared__ double sTau[PW];
+  __shared__ double sInv[PW];
+  __shared__ int sbad;
+
+  const int w = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int c0 = w * PW;
+  const int ncol = min(PW, dh - c0);
+  constexpr int RG = NT / PW;  // row groups
+  const int cg = tid % PW, rg = tid / PW;
+
+  for (int e = tid; e < PW * d; e += NT) {
+    const int c = e / d, r = e % d;
+    sC[c * d + r] = (c < ncol) ? a.B[r + (long)(c0 + c) * a.ldb] : 0.0;
+  }
+  if (tid == 0) sbad = 0;
+  __syncthreads();
+
+  // ---- apply the reflectors of the panels before mine ----
+  for (int p = 0; p < w; ++p) {
+    const int p0 = p * PW;
+    const int pc = min(PW, dh - p0);
+    if (tid == 0) {
+      long spins = 0;
+      while (load_agent_i32(a.flags + p) == 0) {
+        if (++spins > kSpinLimit) { sbad = 1; break; }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __syncthreads();
+    if (sbad) {
+      if (tid == 0) store_agent_i32(a.status, QRCP_ERR_TIMEOUT);
+      return;
+    }
+    __threadfence();
+    if constexpr (PW == 32) {
+      apply_panel_mfma(sC, d, a.V, p0, pc, a.T + (long)p * PW * PW, sV, sW, sT, sPart);
+    } else {
+      for (int e = tid; e < PW * PW; e += NT) sT[e] = a.T[(long)p * PW * PW + e];
+      for (int e = tid; e < PW * PW; e += NT) sW[e] = 0.0;
+      __syncthreads();
+      for (int r0 = p0; r0 < d; r0 += VCH) {
+        const int rows = min(VCH, d - r0);
+        for (int e = tid; e < VCH * PW; e += NT) {
+          const int rr = e % VCH, aa = e / VCH;
+          sV[aa * VCH + rr] = (rr < rows && aa < pc) ? a.V[(r0 + rr) + (long)(p0 + aa) * d] : 0.0;
+        }
+        __syncthreads();
+        for (int e = tid; e < PW * PW; e += NT) {
+          const int aa = e / PW, c = e % PW;
+          double s = 0.0;
+          for (int rr = 0; rr < rows; ++rr) s += sV[aa * VCH + rr] * sC[c * d + r0 + rr];
+          sW[aa * PW + c] += s;
+        }
+        __syncthreads();
+      }
+      for (int e = tid; e < PW * PW; e += NT) {
+        const int aa = e / PW, c = e % PW;
+        double s = 0.0;
+        for (int t = 0; t <= aa; ++t) s += sT[t + aa * PW] * sW[t * PW + c];
+        sPart[aa * PW + c] = s;
+      }
+      __syncthreads();
+      for (int r0 = p0; r0 < d; r0 += VCH) {
+        const int rows = min(VCH, d - r0);
+        for (int e = tid; e < VCH * PW; e += NT) {
+          const int rr = e % VCH, aa = e / VCH;
+          sV[aa * VCH + rr] = (rr < rows && aa < pc) ? a.V[(r0 + rr) + (long)(p0 + aa) * d] : 0.0;
+        }
+        __syncthreads();
+        for (int e = tid; e < VCH * PW; e += NT) {
+          const int rr = e % VCH, c = e / VCH;
+          if (rr < rows) {
+            double s = 0.0;
+            for (int aa = 0; aa < pc; ++aa) s += sV[aa * VCH + rr] * sPart[aa * PW + c];
+            sC[c * d + r0 + rr] -= s;
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+
+  // ---- factor my panel: one fused reduction per column ----
+  // For column jj (diagonal row rj) every thread (rg, c) sums x_r(jj) x_r(c)
+  // over its rows r > rj; slot c = jj is ||x||^2.  With v = x / (alpha - beta)
+  // the reflector acts on column c through w_c = x_rj(c) + s_c / (alpha - beta).
+  // Column jj itself is scaled to v when the panel is published.
+  for (int jj = 0; jj < ncol; ++jj) {
+    const int rj = c0 + jj;
+    const double* xj = sC + jj * d;
+    {
+      double s = 0.0;
+      if (cg >= jj && cg < ncol)
+        for (int r = rj + 1 + rg; r < d; r += RG) s += xj[r] * sC[cg * d + r];
+      sPart[rg * PW + cg] = s;
+    }
+    __syncthreads();
+    if (tid < PW) {
+      double t = 0.0;
+      for (int q = 0; q < RG; ++q) t += sPart[q * PW + tid];
+      sW[tid] = t;
+    }
+    __syncthreads();
+    const double xx = sW[jj];
+    const double alpha = xj[rj];
+    double beta = alpha, tau = 0.0, inv = 1.0;
+    if (xx != 0.0) {
+      const double nrm = sqrt(alpha * alpha + xx);
+      beta = (alpha < 0.0) ? nrm : -nrm;
+      tau = (beta - alpha) / beta;
+      inv = alpha - beta;
+    }
+    if (tau != 0.0 && cg > jj && cg < ncol) {
+      const double wc = sC[cg * d + rj] + sW[cg] / inv;
+      const double f = tau * wc;
+      if (rg == 0) sC[cg * d + rj] -= f;
+      const double fv = f / inv;
+      for (int r = rj + 1 + rg; r < d; r += RG) sC[cg * d + r] -= fv * xj[r];
+    }
+    if (tid == 0) {
+      sTau[jj] = tau;
+      sInv[jj] = (xx != 0.0) ? inv : 0.0;
+      a.tau[rj] = tau;
+      a.R[rj + (long)rj * a.ldr] = beta;
+    }
+    __syncthreads();
+  }
+
+  // ---- publish V_p (clean), R part above the diagonal, and T_p ----
+  for (int e = tid; e < PW * d; e += NT) {
+    const int c = e / d, r = e % d;
+    if (c < ncol) {
+      const int rc = c0 + c;
+      double v = sC[c * d + r];
+      if (r > rc) v = (sInv[c] != 0.0) ? v / sInv[c] : 0.0;
+      sC[c * d + r] = (r == rc) ? 1.0 : v;   // keep the scaled vector for T below
+      a.V[r + (long)rc * d] = (r < rc) ? 0.0 : (r == rc ? 1.0 : v);
+      if (r < rc) a.R[r + (long)rc * a.ldr] = v;
+      else if (r > rc) a.R[r + (long)rc * a.ldr] = 0.0;
+    }
+  }
+  __syncthreads();
+  // T_p by the LARFT recurrence (robust to tau = 0): G = V^T V first
+  for (int e = tid; e < PW * PW; e += NT) {
+    const int i = e / PW, j = e % PW;
+    double s = 0.0;
+    if (i < j && j < ncol) {
+      const int rjj = c0 + j;
+      // V(:, i)^T V(:, j): rows >= rjj (V(r, j) = 0 above rjj, 1 at rjj)
+      s = sC[i * d + rjj];
+      for (int r = rjj + 1; r < d; ++r) s += sC[i * d + r] * sC[j * d + r];
+    }
+    sW[i * PW + j] = s;  // G(i, j) for i < j
+  }
+  __syncthreads();
+  if (tid < 64) {
+    // sequential over columns j, parallel over rows i < j (one wave)
+    for (int j = 0; j < PW; ++j) {
+      const double tj = (j < ncol) ? sTau[j] : 0.0;
+      double val = 0.0;
+      const int i = tid;
+      if (i < j) {
+        for (int t = i; t < j; ++t) val += sT[i + t * PW] * sW[t * PW + j];
+        val = -tj * val;
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (i < j) sT[i + j * PW] = val;
+      if (i == j) sT[j + j * PW] = tj;
+      if (i > j && i < PW) sT[i + j * PW] = 0.0;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < PW * PW; e += NT) a.T[(long)w * PW * PW + e] = sT[e];
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) store_agent_i32(a.flags + w, 1);
+}
+
+}  // namespace
+
+static int head_pw(int d) { return d <= 320 ? 32 : (d <= 640 ? 16 : 8); }
+
+size_t sketch_qr_ws_bytes(int d, i64 ni) {
+  const int dh = (int)std::min((i64)d, ni);
+  const int pw = head_pw(d);
+  const int np = (dh + pw - 1) / pw;
+  size_t b = 0;
+  b += (size_t)d * dh * 8;          // V
+  b += (size_t)dh * 8;              // tau
+  b += (size_t)np * pw * pw * 8;    // T panels
+  b += (size_t)dh * dh * 8;         // V^T V -> T full
+  b += (size_t)dh * dh * 8;         // T full
+  b += (size_t)dh * d * 8;          // X = T V^T
+  b += (size_t)d * d * 8;           // Q
+  b += (size_t)np * 4 + 256;        // flags
+  b += gemm_splitk_bytes(dh, dh, 64);
+  return b + 8 * 64;
+}
+
+int run_sketch_qr(const double* B, int d, i64 ni, i64 ldb, double* R, i64 ldr, void* ws,
+                  size_t ws_bytes, int* status_dev, hipStream_t st) {
+  if (d <= 0 || ni <= 0) return QRCP_OK;
+  if (d > 1280) return QRCP_ERR_UNSUPPORTED;
+  if (ws_bytes < sketch_qr_ws_bytes(d, ni)) return QRCP_ERR_WORKSPACE;
+  const int dh = (int)std::min((i64)d, ni);
+  const int pw = head_pw(d);
+  const int np = (dh + pw - 1) / pw;
+  char* p = (char*)ws;
+  auto take = [&](size_t bytes) { char* q = p; p += (bytes + 255) / 256 * 256; return q; };
+  double* V = (double*)take((size_t)d * dh * 8);
+  double* tau = (double*)take((size_t)dh * 8);
+  double* Tp = (double*)take((size_t)np * pw * pw * 8);
+  double* G = (double*)take((size_t)dh * dh * 8);
+  double* T = (double*)take((size_t)dh * dh * 8);
+  double* X = (double*)take((size_t)dh * d * 8);
+  double* Q = (double*)take((size_t)d * d * 8);
+  int* flags = (int*)take((size_t)(np + 1) / 2 * 8);
+  double* split = (double*)take(gemm_splitk_bytes(dh, dh, 64));
+  const size_t split_bytes = gemm_splitk_bytes(dh, dh, 64);
+
+  QRCP_TRY(launch_fill_u64((uint64_t*)flags, (np + 1) / 2, 0ull, st));
+  HeadArgs args{B, (long)ldb, d, dh, pw, R, (long)ldr, V, tau, Tp, flags, status_dev};
+  void* params[] = {&args};
+  const size_t smem = ((size_t)pw * d + 64 * pw + 2 * pw * pw + std::max<size_t>((size_t)pw * pw, NT)) * 8;
+  const void* fn = pw == 32 ? (const void*)sketch_head_kernel<32>
+                 : pw == 16 ? (const void*)sketch_head_kernel<16>
+                            : (const void*)sketch_head_kernel<8>;
+  QRCP_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  QRCP_TRY(launch_resident(fn, dim3(np), dim3(NT), params, smem, st));
+
+  if (ni > dh) {
+    // T = (diag(1/tau) + striu(V^T V))^{-1}
+    GemmArgs g;
+    g.M = dh; g.N = dh; g.K = d; g.A = V; g.lda = d; g.B = V; g.ldb = d; g.C = G; g.ldc = dh;
+    QRCP_TRY(gemm(true, false, Prec::F64, g, split, split_bytes, st));
+    QRCP_TRY(launch_ut_tinv(G, dh, tau, dh, st));
+    QRCP_TRY(launch_trinv_upper(G, dh, dh, T, dh, st));
+    QRCP_TRY(launch_ut_zero_diag(T, dh, tau, dh, st));
+    // X = T V^T (dh x d)
+    GemmArgs x;
+    x.M = dh; x.N = d; x.K = dh; x.A = T; x.lda = dh; x.B = V; x.ldb = d; x.C = X; x.ldc = dh;
+    QRCP_TRY(gemm(false, true, Prec::F64, x, nullptr, 0, st));
+    // Q = I - V X
+    QRCP_TRY(launch_set_identity(Q, d, d, st));
+    GemmArgs q;
+    q.M = d; q.N = d; q.K = dh; q.alpha = -1.0; q.beta = 1.0;
+    q.A = V; q.lda = d; q.B = X; q.ldb = dh; q.C = Q; q.ldc = d;
+    QRCP_TRY(gemm(false, false, Prec::F64, q, nullptr, 0, st));
+    // R_tail = Q^T B_tail
+    GemmArgs r;
+    r.M = d; r.N = (int)(ni - dh); r.K = d;
+    r.A = Q; r.lda = d; r.B = B + (long)dh * ldb; r.ldb = ldb; r.C = R + (long)dh * ldr; r.ldc = ldr;
+    QRCP_TRY(gemm(true, false, Prec::F64, r, nullptr, 0, st));
+  }
+  return QRCP_OK;
+}
+
+}  // namespace qrcp

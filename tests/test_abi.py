@@ -1,0 +1,72 @@
+"""The C ABI library loads, exports every declared symbol and rejects bad
+arguments on the host (no GPU needed: these calls return before any launch)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qrcp.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(qrcp_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2507_00976_amd import qrcp
+    return qrcp
+
+
+def test_every_declared_symbol_is_exported(lib):
+    raw = ctypes.CDLL(lib.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 18
+    for name in names:
+        assert hasattr(raw, name), name
+    assert set(names) == set(lib.EXPORTED)
+
+
+def test_status_strings(lib):
+    for code in range(0, 6):
+        assert lib.status_string(code)
+    assert lib.status_string(-3) == "illegal argument"
+
+
+def test_workspace_size_is_positive_and_monotone(lib):
+    a = lib.workspace_size(1024, 512, 64, 1.25)
+    b = lib.workspace_size(2048, 512, 64, 1.25)
+    assert 0 < a < b
+    assert lib.workspace_size(1024, 512, 0, 1.25) == 0
+    assert lib.workspace_size(1024, 512, 64, 0.5) == 0
+    assert lib.geqrf_workspace_size(1024, 512, 64) > 0
+
+
+def test_illegal_arguments_rejected_before_launch(lib):
+    L = lib._lib
+    r = ctypes.c_int64(0)
+    nul = None
+    # m < 0, n < 0, lda < m, block 0, gamma < 1, tol < 0, rank NULL
+    assert L.qrcp_factor(nul, -1, 4, 4, 2, 1.25, 1, 0.0, nul, nul, ctypes.byref(r), None, nul, 0, nul) == -2
+    assert L.qrcp_factor(nul, 4, -1, 4, 2, 1.25, 1, 0.0, nul, nul, ctypes.byref(r), None, nul, 0, nul) == -3
+    assert L.qrcp_factor(nul, 8, 4, 4, 2, 1.25, 1, 0.0, nul, nul, ctypes.byref(r), None, nul, 0, nul) == -4
+    assert L.qrcp_factor(nul, 8, 4, 8, 0, 1.25, 1, 0.0, nul, nul, ctypes.byref(r), None, nul, 0, nul) == -5
+    assert L.qrcp_factor(nul, 8, 4, 8, 2, 0.9, 1, 0.0, nul, nul, ctypes.byref(r), None, nul, 0, nul) == -6
+    assert L.qrcp_factor(nul, 8, 4, 8, 2, 1.25, 1, -1.0, nul, nul, ctypes.byref(r), None, nul, 0, nul) == -8
+    assert L.qrcp_factor(nul, 8, 4, 8, 2, 1.25, 1, 0.0, nul, nul, None, None, nul, 0, nul) == -11
+    # wide matrices are not supported; empty ones are a no-op
+    assert L.qrcp_factor(nul, 4, 8, 4, 2, 1.25, 1, 0.0, nul, nul, ctypes.byref(r), None, nul, 0, nul) == lib.QRCP_ERR_UNSUPPORTED
+    assert L.qrcp_factor(nul, 4, 0, 4, 2, 1.25, 1, 0.0, nul, nul, ctypes.byref(r), None, nul, 0, nul) == 0
+    # bad options
+    o = lib.QrcpOpts(ctypes.sizeof(lib.QrcpOpts), 3, 0, 0, 0)
+    assert L.qrcp_factor(nul, 8, 4, 8, 2, 1.25, 1, 0.0, nul, nul, ctypes.byref(r), ctypes.byref(o), nul, 0, nul) == -12
+    # missing workspace is reported, not dereferenced
+    fake = ctypes.c_void_p(16)
+    assert L.qrcp_factor(fake, 8, 4, 8, 2, 1.25, 1, 0.0, fake, fake, ctypes.byref(r), None, nul, 0, nul) == lib.QRCP_ERR_WORKSPACE
+    assert L.qrcp_geqrf(nul, 4, 8, 4, nul, 2, nul, 0, nul) == lib.QRCP_ERR_UNSUPPORTED
+    assert L.qrcp_geqrf(nul, 8, 4, 2, nul, 2, nul, 0, nul) == -4
+    assert L.qrcp_lu_pivots(nul, 0, 4, 4, nul, nul, nul, 0, nul) == -2
+    assert L.qrcp_sketch_update(nul, 8, 9, 4, 8, nul, 8, nul, 8, nul, 0, nul) == -3
