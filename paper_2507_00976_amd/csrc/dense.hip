@@ -2,6 +2,7 @@
 // inverses, Cholesky, the sign-modified LU of the reconstruction, copies).
 #include "common.hpp"
 #include "kernels.hpp"
+#include "wave32.hpp"
 
 namespace qrcp {
 
@@ -73,52 +74,6 @@ int launch_philox(const uint32_t* ctr, i64 count, uint32_t k0, uint32_t k1, uint
 }
 
 // ---------------------------------------------------------------------------
-// X = R^{-1}, R upper triangular n x n.  One wave per column j: column-oriented
-// back substitution on x = e_j held in registers (lane l owns rows l + 64 s).
-// ---------------------------------------------------------------------------
-template <int NR>
-__global__ __launch_bounds__(256) void trinv_upper_kernel(const double* R, long ldr, int n,
-                                                          double* X, long ldx) {
-  const int lane = threadIdx.x & 63;
-  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (j >= n) return;
-  double x[NR];
-#pragma unroll
-  for (int s = 0; s < NR; ++s) x[s] = (s * 64 + lane == j) ? 1.0 : 0.0;
-  for (int i = j; i >= 0; --i) {
-    const int si = i >> 6, li = i & 63;
-    double xi = 0.0;
-#pragma unroll
-    for (int s = 0; s < NR; ++s)
-      if (s == si) xi = __shfl(x[s], li, 64);
-    xi = xi / R[i + (long)i * ldr];
-#pragma unroll
-    for (int s = 0; s < NR; ++s) {
-      const int r = s * 64 + lane;
-      if (r == i) x[s] = xi;
-      else if (r < i) x[s] -= xi * R[r + (long)i * ldr];
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < NR; ++s) {
-    const int r = s * 64 + lane;
-    if (r < n) X[r + (long)j * ldx] = (r <= j) ? x[s] : 0.0;
-  }
-}
-
-int launch_trinv_upper(const double* R, i64 ldr, int n, double* X, i64 ldx, hipStream_t st) {
-  if (n <= 0) return QRCP_OK;
-  dim3 grid((n + 3) / 4), block(256);
-  if (n <= 64) hipLaunchKernelGGL(trinv_upper_kernel<1>, grid, block, 0, st, R, ldr, n, X, ldx);
-  else if (n <= 256) hipLaunchKernelGGL(trinv_upper_kernel<4>, grid, block, 0, st, R, ldr, n, X, ldx);
-  else if (n <= 512) hipLaunchKernelGGL(trinv_upper_kernel<8>, grid, block, 0, st, R, ldr, n, X, ldx);
-  else if (n <= 1024) hipLaunchKernelGGL(trinv_upper_kernel<16>, grid, block, 0, st, R, ldr, n, X, ldx);
-  else return QRCP_ERR_UNSUPPORTED;
-  QRCP_LAUNCHED("trinv_upper");
-  return QRCP_OK;
-}
-
-// ---------------------------------------------------------------------------
 // Compact WY factor from Y^T Y and tau (UT transform: T^{-1} = diag(1/tau) +
 // strictly-upper(Y^T Y)).  A zero tau (H_j = I) decouples index j: its row and
 // column are cleared and T(j,j) = 0 afterwards.
@@ -153,26 +108,37 @@ int launch_ut_zero_diag(double* T, i64 ldt, const double* tau, int n, hipStream_
 }
 
 // ---------------------------------------------------------------------------
-// Blocked right-looking factorizations of a small square matrix (n <= 1024) by
-// one 256-thread workgroup.  Per 32-column step: the 32 x 32 diagonal block is
-// factored in LDS by one wave, the off-diagonal panels by one thread per row or
-// column, and the trailing block is updated in 64 x 64 tiles on the FP64
-// matrix cores (LDS-staged operands).
+// LDS-staged 64 x 64 output tiles on the FP64 matrix cores, used by the
+// single-workgroup factorizations below (256 threads = 4 waves, each wave a
+// 32 x 32 quarter of the tile).
 // ---------------------------------------------------------------------------
-constexpr int SB = 32;
-constexpr int TT = 64;  // trailing tile
+constexpr int SB = 32;  // diagonal block
+constexpr int TT = 64;  // output tile
 
 typedef double dv4 __attribute__((ext_vector_type(4)));
 
 // C(0:M, 0:N) (-)= A B for one tile: A is M x kk staged as sA[t][i], B is
-// kk x N staged as sB[t][j] (kk <= 32, M, N <= 64).  Executed by the 4 waves
-// of the 256-thread workgroup on the FP64 matrix cores.  assign: C = A B,
-// else C -= A B.
+// kk x N staged as sB[t][j] (kk <= 32, M, N <= 64).  assign: C = A B, else
+// C -= A B; the C values are read before the products so that their latency
+// overlaps the matrix-core work.
 __device__ __forceinline__ void tile_mm(double* C, long ldc, int M, int N, int kk,
                                         const double (*sA)[TT], const double (*sB)[TT],
                                         bool assign) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w & 1, wn = w >> 1;
+  double old[2][2][4];
+  if (!assign) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = wm * 32 + a * 16 + (lane & 15);
+          const int j = wn * 32 + b * 16 + 4 * r + (lane >> 4);
+          old[a][b][r] = (i < M && j < N) ? C[i + (long)j * ldc] : 0.0;
+        }
+  }
   dv4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -200,80 +166,221 @@ __device__ __forceinline__ void tile_mm(double* C, long ldc, int M, int N, int k
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int j = wn * 32 + b * 16 + 4 * r + (lane >> 4);
-        if (i < M && j < N) {
-          double* c = C + i + (long)j * ldc;
-          *c = assign ? acc[a][b][r] : *c - acc[a][b][r];
-        }
+        if (i < M && j < N) C[i + (long)j * ldc] = assign ? acc[a][b][r] : old[a][b][r] - acc[a][b][r];
       }
   }
 }
 
-// Generic tiled product over a rows x cols output: C (-)= A B with A(i, t)
-// and B(t, j) read through accessors (t < kk <= 32).  upper_only skips tiles
-// strictly below the diagonal.  Tiles are staged in LDS one at a time.
+// C (-)= A B over a rows x cols output in 64 x 64 tiles, with A(i, t) and
+// B(t, j) read through accessors (t < kk <= 32).  upper_only skips tiles
+// strictly below the diagonal.  The operands of the next tile are loaded
+// into registers while the current tile is multiplied, so the operands must
+// not overlap the output.  blockDim.x must be 256.
 template <typename FA, typename FB>
 __device__ __forceinline__ void tiled_mm(double* C, long ldc, int rows, int cols, int kk,
                                          bool upper_only, bool assign, FA fa, FB fb,
                                          double (*sA)[TT], double (*sB)[TT]) {
+  constexpr int PER = SB * TT / 256;
   const int tid = threadIdx.x;
-  const int ntr = (rows + TT - 1) / TT, ntc = (cols + TT - 1) / TT;
-  for (int ti = 0; ti < ntr * ntc; ++ti) {
-    const int tr = ti % ntr, tc = ti / ntr;
-    if (upper_only && tr > tc) continue;   // uniform
-    const int r0 = tr * TT, c0 = tc * TT;
+  const int ntr = (rows + TT - 1) / TT, ntc = (cols + TT - 1) / TT, nt = ntr * ntc;
+  auto advance = [&](int ti) {
+    while (ti < nt && upper_only && (ti % ntr) > (ti / ntr)) ++ti;
+    return ti;
+  };
+  double ra[PER], rb[PER];
+  auto load = [&](int ti) {
+    const int r0 = (ti % ntr) * TT, c0 = (ti / ntr) * TT;
     const int M = min(TT, rows - r0), N = min(TT, cols - c0);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + q * 256, t = e / TT, x = e % TT;
+      ra[q] = (t < kk && x < M) ? fa(r0 + x, t) : 0.0;
+      rb[q] = (t < kk && x < N) ? fb(t, c0 + x) : 0.0;
+    }
+  };
+  int ti = advance(0);
+  if (ti < nt) load(ti);
+  while (ti < nt) {
     __syncthreads();
-    for (int e = tid; e < SB * TT; e += blockDim.x) {
-      const int t = e / TT, x = e % TT;
-      sA[t][x] = (t < kk && x < M) ? fa(r0 + x, t) : 0.0;
-      sB[t][x] = (t < kk && x < N) ? fb(t, c0 + x) : 0.0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + q * 256, t = e / TT, x = e % TT;
+      sA[t][x] = ra[q];
+      sB[t][x] = rb[q];
     }
     __syncthreads();
-    tile_mm(C + r0 + (long)c0 * ldc, ldc, M, N, kk, sA, sB, assign);
+    const int tn = advance(ti + 1);
+    if (tn < nt) load(tn);
+    const int r0 = (ti % ntr) * TT, c0 = (ti / ntr) * TT;
+    tile_mm(C + r0 + (long)c0 * ldc, ldc, min(TT, rows - r0), min(TT, cols - c0), kk, sA, sB,
+            assign);
+    ti = tn;
   }
   __syncthreads();
 }
 
-// One wave: X = inverse of the upper triangle of D (nb x nb) into sX.
-__device__ __forceinline__ void wave_inv_upper(const double (*D)[SB + 1], double (*X)[SB + 1], int nb) {
-  const int j = threadIdx.x & 63;
-  if (j < nb) {
-    for (int i = nb - 1; i >= 0; --i) {
-      double v;
-      if (i > j) {
-        v = 0.0;
-      } else if (i == j) {
-        v = 1.0 / D[i][i];
-      } else {
-        double sacc = 0.0;
-        for (int l = i + 1; l <= j; ++l) sacc += D[i][l] * X[l][j];
-        v = -sacc / D[i][i];
-      }
-      X[i][j] = v;
+// ---------------------------------------------------------------------------
+// X = R^{-1}, R upper triangular n x n (only its upper triangle is read).
+// Blocked by 32: the diagonal blocks are inverted in registers, one wave per
+// block (trinv_diag_kernel); then each block column J of X is finished by one
+// workgroup going up the block rows, X_IJ = -X_II sum_{K=I+1..J} R_IK X_KJ,
+// on the FP64 matrix cores with the finished blocks of the column kept in LDS
+// (trinv_offdiag_kernel).  Orders above 512 use one wave per column.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void trinv_diag_kernel(const double* R, long ldr, int n,
+                                                         double* X, long ldx) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int p0 = blockIdx.x * W32, nb = min(W32, n - p0);
+  if (tid < 64) {
+    double x[W32], y[W32];
+#pragma unroll
+    for (int r = 0; r < W32; ++r)
+      x[r] = (lane < nb && r <= lane) ? R[(p0 + r) + (long)(p0 + lane) * ldr] : 0.0;
+    wave_inv_upper32_col(x, y, nb);
+    if (lane < nb) {
+#pragma unroll
+      for (int r = 0; r < W32; ++r)
+        if (r < nb) X[(p0 + r) + (long)(p0 + lane) * ldx] = y[r];
     }
+  }
+  // strictly lower part of this block column
+  const long below = n - p0 - nb;
+  for (long e = tid; e < below * nb; e += blockDim.x)
+    X[(p0 + nb + e % below) + (long)(p0 + e / below) * ldx] = 0.0;
+}
+
+template <int NBLK>
+__global__ __launch_bounds__(256) void trinv_offdiag_kernel(const double* R, long ldr, int n,
+                                                            double* X, long ldx) {
+  __shared__ double sCol[NBLK][W32][W32 + 1];  // finished X_KJ of this column, [row][col]
+  __shared__ double sS[W32][W32 + 1];
+  __shared__ double sXd[W32][W32 + 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w & 1, wn = w >> 1;  // this wave's 16 x 16 quarter of a 32 x 32 block
+  const int i16 = lane & 15, k4 = lane >> 4;
+  const int J = blockIdx.x + 1, pJ = J * W32, nbJ = min(W32, n - pJ);
+  for (int e = tid; e < W32 * W32; e += 256) {
+    const int r = e % W32, c = e / W32;
+    sCol[J][r][c] = (r < nbJ && c < nbJ) ? X[(pJ + r) + (long)(pJ + c) * ldx] : 0.0;
+  }
+  __syncthreads();
+  for (int I = J - 1; I >= 0; --I) {
+    const int pI = I * W32;
+    double xd[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * 256;
+      xd[q] = X[(pI + e % W32) + (long)(pI + e / W32) * ldx];
+    }
+    // S = sum_K R_IK X_KJ; A(i, k) = R(pI + 16 wm + i, pK + k) straight from memory,
+    // next block's operands loaded while the current one is multiplied
+    const double* arow = R + (pI + 16 * wm + i16);
+    double an[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int col = (I + 1) * W32 + 4 * s + k4;
+      an[s] = (col < n) ? arow[(long)col * ldr] : 0.0;
+    }
+    dv4 acc = dv4{0.0, 0.0, 0.0, 0.0};
+    for (int K = I + 1; K <= J; ++K) {
+      double a[8];
+#pragma unroll
+      for (int s = 0; s < 8; ++s) a[s] = an[s];
+      if (K < J) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const int col = (K + 1) * W32 + 4 * s + k4;
+          an[s] = (col < n) ? arow[(long)col * ldr] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], sCol[K][4 * s + k4][16 * wn + i16], acc,
+                                                   0, 0, 0);
+    }
+    // D(i, j) sits in lane j + 16 (i % 4), register i / 4
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sS[16 * wm + 4 * r + k4][16 * wn + i16] = acc[r];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * 256;
+      sXd[e % W32][e / W32] = xd[q];
+    }
+    __syncthreads();
+    dv4 acc2 = dv4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+      acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(sXd[16 * wm + i16][4 * s + k4],
+                                                  sS[4 * s + k4][16 * wn + i16], acc2, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * wm + 4 * r + k4, j = 16 * wn + i16;
+      const double v = -acc2[r];
+      sCol[I][i][j] = v;
+      if (j < nbJ) X[(pI + i) + (long)(pJ + j) * ldx] = v;
+    }
+    __syncthreads();
   }
 }
 
-// One wave: X = inverse of the unit lower triangle of D (nb x nb) into sX.
-__device__ __forceinline__ void wave_inv_unit_lower(const double (*D)[SB + 1], double (*X)[SB + 1],
-                                                    int nb) {
-  const int j = threadIdx.x & 63;
-  if (j < nb) {
-    for (int i = 0; i < nb; ++i) {
-      double v;
-      if (i < j) {
-        v = 0.0;
-      } else if (i == j) {
-        v = 1.0;
-      } else {
-        double sacc = 0.0;
-        for (int l = j; l < i; ++l) sacc += D[i][l] * X[l][j];
-        v = -sacc;
-      }
-      X[i][j] = v;
+template <int NR>
+__global__ __launch_bounds__(256) void trinv_upper_kernel(const double* R, long ldr, int n,
+                                                          double* X, long ldx) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= n) return;
+  double x[NR];
+#pragma unroll
+  for (int s = 0; s < NR; ++s) x[s] = (s * 64 + lane == j) ? 1.0 : 0.0;
+  for (int i = j; i >= 0; --i) {
+    const int si = i >> 6, li = i & 63;
+    double xi = 0.0;
+#pragma unroll
+    for (int s = 0; s < NR; ++s)
+      if (s == si) xi = __shfl(x[s], li, 64);
+    xi = xi / R[i + (long)i * ldr];
+#pragma unroll
+    for (int s = 0; s < NR; ++s) {
+      const int r = s * 64 + lane;
+      if (r == i) x[s] = xi;
+      else if (r < i) x[s] -= xi * R[r + (long)i * ldr];
     }
   }
+#pragma unroll
+  for (int s = 0; s < NR; ++s) {
+    const int r = s * 64 + lane;
+    if (r < n) X[r + (long)j * ldx] = (r <= j) ? x[s] : 0.0;
+  }
 }
+
+int launch_trinv_upper(const double* R, i64 ldr, int n, double* X, i64 ldx, hipStream_t st) {
+  if (n <= 0) return QRCP_OK;
+  if (n > 1024) return QRCP_ERR_UNSUPPORTED;
+  if (n > 512) {
+    hipLaunchKernelGGL(trinv_upper_kernel<16>, dim3((n + 3) / 4), dim3(256), 0, st, R, ldr, n, X,
+                       ldx);
+    QRCP_LAUNCHED("trinv_upper");
+    return QRCP_OK;
+  }
+  const int nblk = (n + W32 - 1) / W32;
+  hipLaunchKernelGGL(trinv_diag_kernel, dim3(nblk), dim3(256), 0, st, R, ldr, n, X, ldx);
+  QRCP_LAUNCHED("trinv_diag");
+  if (nblk > 1) {
+    const dim3 g(nblk - 1), b(256);
+    if (nblk <= 8) hipLaunchKernelGGL(trinv_offdiag_kernel<8>, g, b, 0, st, R, ldr, n, X, ldx);
+    else if (nblk <= 10) hipLaunchKernelGGL(trinv_offdiag_kernel<10>, g, b, 0, st, R, ldr, n, X, ldx);
+    else hipLaunchKernelGGL(trinv_offdiag_kernel<16>, g, b, 0, st, R, ldr, n, X, ldx);
+    QRCP_LAUNCHED("trinv_offdiag");
+  }
+  return QRCP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Blocked right-looking factorizations of a small square matrix (n <= 1024) by
+// one 256-thread workgroup.  Per 32-column step the diagonal block is factored
+// and inverted in the registers of one wave, the off-diagonal panels and the
+// trailing block are updated in 64 x 64 tiles on the FP64 matrix cores.
+// ---------------------------------------------------------------------------
 
 // Cholesky G = R^T R, upper.  *info = columns factored (n if no breakdown).
 __global__ __launch_bounds__(256) void potrf_upper_kernel(double* G, long ldg, int n, int* info) {
@@ -282,36 +389,34 @@ __global__ __launch_bounds__(256) void potrf_upper_kernel(double* G, long ldg, i
   __shared__ double sA[SB][TT];
   __shared__ double sB[SB][TT];
   __shared__ int brk;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
   if (tid == 0) brk = -1;
   for (int p0 = 0; p0 < n; p0 += SB) {
-    const int nb = min(SB, n - p0);
+    const int nb = min(SB, n - p0), rest = n - p0 - nb;
     __syncthreads();
     for (int e = tid; e < SB * SB; e += blockDim.x) {
       const int tr = e % SB, tc = e / SB;
-      if (tr < nb && tc < nb) sD[tr][tc] = (tr <= tc) ? G[(p0 + tr) + (long)(p0 + tc) * ldg] : 0.0;
+      sD[tr][tc] = (tr < nb && tc < nb && tr <= tc) ? G[(p0 + tr) + (long)(p0 + tc) * ldg] : 0.0;
     }
     __syncthreads();
     if (tid < 64) {
-      const int lane = tid;
-      for (int t = 0; t < nb; ++t) {
-        const double dd = sD[t][t];
-        if (!(dd > 0.0)) {
-          if (lane == 0) brk = p0 + t;
-          break;
+      double x[W32];
+#pragma unroll
+      for (int r = 0; r < W32; ++r) x[r] = (lane < SB) ? sD[r][lane] : 0.0;
+      const int t = wave_potrf32_col(x, nb);
+      if (lane < SB) {
+#pragma unroll
+        for (int r = 0; r < W32; ++r) sD[r][lane] = x[r];
+      }
+      if (t < nb) {
+        if (lane == 0) brk = p0 + t;
+      } else if (rest > 0) {
+        double y[W32];
+        wave_inv_upper32_col(x, y, nb);
+        if (lane < SB) {
+#pragma unroll
+          for (int r = 0; r < W32; ++r) sX[r][lane] = y[r];
         }
-        const double r = sqrt(dd);
-        __builtin_amdgcn_wave_barrier();
-        if (lane == t) sD[t][t] = r;
-        if (lane > t && lane < nb) sD[t][lane] /= r;
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        if (lane > t && lane < nb) {
-          const double u = sD[t][lane];
-          for (int rr = t + 1; rr <= lane; ++rr) sD[rr][lane] -= sD[t][rr] * u;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
       }
     }
     __syncthreads();
@@ -320,10 +425,7 @@ __global__ __launch_bounds__(256) void potrf_upper_kernel(double* G, long ldg, i
       if (tr < nb && tc < nb && tr <= tc) G[(p0 + tr) + (long)(p0 + tc) * ldg] = sD[tr][tc];
     }
     if (brk >= 0) break;
-    const int rest = n - p0 - nb;
     if (rest > 0) {
-      if (tid < 64) wave_inv_upper(sD, sX, nb);
-      __syncthreads();
       // row panel R12 = R11^{-T} G12 (in place): A(i, t) = R11^{-1}(t, i)
       double* g12 = G + p0 + (long)(p0 + nb) * ldg;
       tiled_mm(g12, ldg, nb, rest, nb, false, true,
@@ -355,38 +457,40 @@ int launch_potrf_upper(double* G, i64 ldg, int n, int* info_dev, hipStream_t st)
 // is divided by the new pivot and the trailing block updated.
 __global__ __launch_bounds__(256) void headlu_kernel(double* Q, long ldq, int k, double* dsig) {
   __shared__ double sD[SB][SB + 1];
-  __shared__ double sX[SB][SB + 1];
+  __shared__ double sXu[SB][SB + 1];
+  __shared__ double sXl[SB][SB + 1];
   __shared__ double sA[SB][TT];
   __shared__ double sB[SB][TT];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
   for (int p0 = 0; p0 < k; p0 += SB) {
-    const int nb = min(SB, k - p0);
+    const int nb = min(SB, k - p0), rest = k - p0 - nb;
     __syncthreads();
     for (int e = tid; e < SB * SB; e += blockDim.x) {
       const int tr = e % SB, tc = e / SB;
-      if (tr < nb && tc < nb) sD[tr][tc] = Q[(p0 + tr) + (long)(p0 + tc) * ldq];
+      sD[tr][tc] = (tr < nb && tc < nb) ? Q[(p0 + tr) + (long)(p0 + tc) * ldq] : 0.0;
     }
     __syncthreads();
     if (tid < 64) {
-      const int lane = tid;  // lane = row of the diagonal block
-      for (int t = 0; t < nb; ++t) {
-        const double a = sD[t][t];
-        const double dj = (a >= 0.0) ? -1.0 : 1.0;
-        const double piv = a - dj;
-        __builtin_amdgcn_wave_barrier();
-        if (lane == t) {
-          sD[t][t] = piv;
-          dsig[p0 + t] = dj;
+      double x[W32];
+#pragma unroll
+      for (int c = 0; c < W32; ++c) x[c] = (lane < SB) ? sD[lane][c] : 0.0;
+      wave_lu32_signmod_row(x, nb, dsig + p0);
+      if (lane < SB) {
+#pragma unroll
+        for (int c = 0; c < W32; ++c) sD[lane][c] = x[c];
+      }
+      if (rest > 0) {
+        double y[W32];
+        wave_inv_upper32_row(x, y, nb);
+        if (lane < SB) {
+#pragma unroll
+          for (int r = 0; r < W32; ++r) sXu[r][lane] = y[r];
         }
-        if (lane > t && lane < nb) sD[lane][t] /= piv;
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        if (lane > t && lane < nb) {
-          const double l = sD[lane][t];
-          for (int c = t + 1; c < nb; ++c) sD[lane][c] -= l * sD[t][c];
+        wave_inv_unit_lower32_row(x, y, nb);
+        if (lane < SB) {
+#pragma unroll
+          for (int r = 0; r < W32; ++r) sXl[r][lane] = y[r];
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
       }
     }
     __syncthreads();
@@ -394,21 +498,16 @@ __global__ __launch_bounds__(256) void headlu_kernel(double* Q, long ldq, int k,
       const int tr = e % SB, tc = e / SB;
       if (tr < nb && tc < nb) Q[(p0 + tr) + (long)(p0 + tc) * ldq] = sD[tr][tc];
     }
-    const int rest = k - p0 - nb;
     if (rest > 0) {
       double* a21 = Q + (p0 + nb) + (long)p0 * ldq;   // rows below the block
       double* a12 = Q + p0 + (long)(p0 + nb) * ldq;   // columns right of the block
       // L21 = A21 U11^{-1}
-      if (tid < 64) wave_inv_upper(sD, sX, nb);
-      __syncthreads();
       tiled_mm(a21, ldq, rest, nb, nb, false, true,
                [&](int i, int t) { return a21[i + (long)t * ldq]; },
-               [&](int t, int j) { return sX[t][j]; }, sA, sB);
+               [&](int t, int j) { return sXu[t][j]; }, sA, sB);
       // U12 = L11^{-1} A12
-      if (tid < 64) wave_inv_unit_lower(sD, sX, nb);
-      __syncthreads();
       tiled_mm(a12, ldq, nb, rest, nb, false, true,
-               [&](int i, int t) { return sX[i][t]; },
+               [&](int i, int t) { return sXl[i][t]; },
                [&](int t, int j) { return a12[t + (long)j * ldq]; }, sA, sB);
       // A22 -= L21 U12
       tiled_mm(Q + (p0 + nb) + (long)(p0 + nb) * ldq, ldq, rest, rest, nb, false, false,
