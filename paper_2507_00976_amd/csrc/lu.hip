@@ -1,27 +1,38 @@
 // Pivot selection of the wide sketch (Alg. 2): GETRF with partial pivoting on
-// X = (M^sk)^T, computed as one cooperative kernel.
+// X = (M^sk)^T, computed as one kernel whose workgroups are all resident.
 //
 // Layout: the d x ni column-major sketch *is* X stored row-major (row t of X =
 // sketch column t, d contiguous doubles), so the transpose of Alg. 2 costs
-// nothing.  The ni rows are spread over G co-resident workgroups (R rows each,
-// TPR threads per row); the current 32-column panel of every row sits in
-// registers, the trailing columns in a working copy in HBM.
+// nothing.  The ni rows are spread over G workgroups of 256 threads, 64*RPT
+// rows each, with a working copy of the rows in HBM.
 //
-// One pivot step = one cross-workgroup exchange: every workgroup publishes its
-// best candidate (|x|, position, row id) and that row's panel values into a
-// record slot owned by (step, workgroup); every workgroup then reads all
-// headers, agrees on the winner (largest |x|, ties to the smallest current
-// position, as IDAMAX), reads the winner's panel values and applies the
-// rank-1 update to its own rows.  Record slots are never reused within a call
-// and are reset to a sentinel bit pattern beforehand, so each 64-bit word is
-// valid as soon as it differs from the sentinel: no flags or fences are needed
-// for the exchange itself.  Row swaps are never performed: each row carries its
-// current position, and the row sitting at position j takes the pivot's
-// position when the pivot leaves (the swap of GETRF).
+// Pivot steps run panel by panel (32 columns).  During the steps of a panel
+// only wave 0 of each workgroup works: lane l holds the panel part of rows
+// l, l+64, ... in registers, shifted left by one column after each step so
+// that the current column is always register 0.  The other three waves join
+// for the blocked trailing update after the panel:
+//   U12 = L11^{-1} X(piv, trail),  X(r, trail) -= L(r, panel) U12
+// (forward substitution in registers, then the product on the FP64 matrix
+// cores).
 //
-// After each panel the trailing columns are updated in the blocked form:
-// U12 = L11^{-1} X(piv, trail), X(r, trail) -= L(r, panel) U12.
+// One pivot step costs one cross-workgroup round trip.  Every workgroup
+// publishes a record for its best candidate: a header (|x|, key = current
+// position and row id, x, the candidate's multiplier for the previous pivot,
+// its value in the next column) and a payload (its panel row).  Every
+// workgroup reads all headers and agrees on the winner (largest |x|, ties to
+// the smallest current position, as IDAMAX).  The header alone is enough to
+// eliminate in the next column at once; the previous pivot's contribution to
+// the remaining panel columns is applied one step late, from the previous
+// winner's payload, which was fetched while the current headers travelled
+// (pivot row j = payload_j - lambda_j * pivot row j-1).  Record slots are
+// never reused within a call and are reset to a sentinel bit pattern
+// beforehand, so each 64-bit word is valid as soon as it differs from the
+// sentinel; every wait is bounded by kSpinLimit.  Row swaps are never
+// performed: each row carries its current position, and the row sitting at
+// position j takes the pivot's position when the pivot leaves (the swap of
+// GETRF).
 #include <climits>
+#include <cstdlib>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -29,21 +40,25 @@
 namespace qrcp {
 
 namespace {
-constexpr int NB = 32;            // panel width
-constexpr int NT = 256;           // threads per workgroup
-constexpr int RW = 2 + NB;        // words per record
-constexpr int TCH = 256;          // trailing columns per chunk
+constexpr int NB = 32;    // panel width
+constexpr int NT = 256;   // threads per workgroup
+constexpr int HW = 5;     // header words
+constexpr int RW = 40;    // words per record: header, NB payload words, padding
+constexpr int TCH = 256;  // trailing columns per chunk
 constexpr uint64_t SENT = 0xFFF0DEADBEEFCAFEull;
 constexpr uint64_t NOCAND = 0x7FFFFFFF00000000ull;
 constexpr uint64_t BADKEY = 0x7FFFFFFE00000000ull;
 constexpr int kMaxGroups = 256;
+constexpr int GQ = kMaxGroups / 64;  // records read per lane
+
+typedef double dv4 __attribute__((ext_vector_type(4)));
 
 struct LuArgs {
   const double* msk;
   long ld;
   int d;
   long ni;
-  double* xw;        // d x ni working copy (ld = d)
+  double* xw;        // ni x d row-major working copy
   uint64_t* rec;     // steps x G x RW words, sentinel-filled
   long* ipiv;
   long* jsk;
@@ -54,260 +69,415 @@ __device__ __forceinline__ bool better(double va, uint64_t ka, double vb, uint64
   return va > vb || (va == vb && ka < kb);
 }
 
-__device__ __forceinline__ uint64_t poll(uint64_t* p, bool& timed_out) {
-  if (timed_out) return 0;
-  uint64_t v = load_agent(p);
-  long spins = 0;
-  while (v == SENT) {
-    if (++spins > kSpinLimit) {
-      timed_out = true;
-      return 0;
-    }
-    __builtin_amdgcn_s_sleep(1);
-    v = load_agent(p);
-  }
-  return v;
-}
-
-// Workgroup argmax of (v, key): every thread gets the result.
-__device__ __forceinline__ void wg_argmax(double& v, uint64_t& key, double* sv, uint64_t* sk) {
+// Wave-wide argmax of (v, key); every lane gets the result.
+__device__ __forceinline__ void wave_argmax(double& v, uint64_t& key) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     const double ov = __shfl_xor(v, o, 64);
     const uint64_t ok = ((uint64_t)(uint32_t)__shfl_xor((int)(key >> 32), o, 64) << 32) |
                         (uint32_t)__shfl_xor((int)(uint32_t)key, o, 64);
-    if (better(ov, ok, v, key)) { v = ov; key = ok; }
+    if (better(ov, ok, v, key)) {
+      v = ov;
+      key = ok;
+    }
   }
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) { sv[w] = v; sk[w] = key; }
-  __syncthreads();
-  v = sv[0];
-  key = sk[0];
-#pragma unroll
-  for (int i = 1; i < NT / 64; ++i)
-    if (better(sv[i], sk[i], v, key)) { v = sv[i]; key = sk[i]; }
 }
 
-__device__ __forceinline__ double canon(double x) { return isnan(x) ? __longlong_as_double(0x7FF8000000000000ll) : x; }
+__device__ __forceinline__ double rdlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFFll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 
-template <int TPR>
+__device__ __forceinline__ uint64_t canon(double x) {
+  return isnan(x) ? 0x7FF8000000000000ull : dbits(x);
+}
+
+__device__ __forceinline__ double cand_value(double x) { return isnan(x) ? -0.5 : fabs(x); }
+
+template <int RPT>
 __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
-  constexpr int R = NT / TPR;
-  constexpr int CPT = NB / TPR;
-  __shared__ double sU[NB][TCH];
-  __shared__ double sLr[R][NB + 1];
-  __shared__ double sL11[NB][NB + 1];
-  __shared__ int sWin[NB];
-  __shared__ double sPiv[NB];
-  __shared__ long sRow[NB];
-  __shared__ double sv[NT / 64];
-  __shared__ uint64_t sk[NT / 64];
-  __shared__ int sflag;
+  constexpr int R = 64 * RPT;
+  __shared__ double sU[NB][TCH];         // U12 chunk
+  __shared__ double sLr[R][NB + 1];      // multipliers of this workgroup's rows
+  __shared__ double sL11[NB][NB + 1];    // multipliers of the panel's pivot rows
+  __shared__ long sRow[NB];              // the panel's pivot rows
+  __shared__ int sAct[R];
+  __shared__ int sBad, sErr;
 
   const int g = blockIdx.x, G = gridDim.x;
-  const int tid = threadIdx.x, rl = tid / TPR, part = tid % TPR;
-  const int lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int i16 = lane & 15, k4 = lane >> 4;
   const int d = a.d;
   const long ni = a.ni;
-  const long row = (long)g * R + rl;
-  const bool valid = row < ni;
   const int steps = (int)min((long)d, ni);
-  long pos = valid ? row : LONG_MAX;
-  bool active = valid;
-  double* xw = a.xw + row * (long)d;
+  const long row0 = (long)g * R;
 
   // working copy of this workgroup's rows + non-finite check
-  bool bad = false;
-  if (valid) {
-    const double* src = a.msk + row * a.ld;
-    for (int c = part; c < d; c += TPR) {
-      const double v = src[c];
-      bad |= !isfinite(v);
-      xw[c] = v;
-    }
+  if (tid == 0) {
+    sBad = 0;
+    sErr = 0;
   }
-  if (tid == 0) sflag = 0;
   __syncthreads();
-  if (bad) sflag = 1;
+  {
+    bool bad = false;
+    const long nrow = min((long)R, ni - row0);
+    for (long e = tid; e < nrow * d; e += NT) {
+      const long r = e / d;
+      const int c = (int)(e % d);
+      const double v = a.msk[(row0 + r) * a.ld + c];
+      bad |= !isfinite(v);
+      a.xw[(row0 + r) * d + c] = v;
+    }
+    if (bad) sBad = 1;
+  }
   __syncthreads();
-  const bool wg_bad = sflag != 0;
+  const bool wg_bad = sBad != 0;
   __threadfence();
 
-  double pv[CPT];
-  bool timed_out = false;
+  // row state (meaningful in wave 0)
+  long row[RPT], pos[RPT];
+  bool act[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    row[q] = row0 + lane + 64 * q;
+    act[q] = row[q] < ni;
+    pos[q] = act[q] ? row[q] : LONG_MAX;
+  }
 
   for (int p0 = 0; p0 < steps; p0 += NB) {
-    // this panel's columns of my row
+    const int ns = min(NB, steps - p0);
+    if (wv == 0) {
+      double x[RPT][NB];
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-      const int c = p0 + part * CPT + q;
-      pv[q] = (active && c < d) ? xw[c] : 0.0;
-    }
+      for (int q = 0; q < RPT; ++q)
 #pragma unroll
-    for (int jl = 0; jl < NB; ++jl) {
-      const int jg = p0 + jl;
-      if (jg < steps) {  // uniform
-        const int qj = jl / CPT, sj = jl % CPT;
-        // ---- local candidate ----
+        for (int t = 0; t < NB; ++t)
+          x[q][t] = (act[q] && p0 + t < d) ? a.xw[row[q] * d + p0 + t] : 0.0;
+      double lprev[RPT];
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) lprev[q] = 0.0;
+      double pprev = 0.0;      // pivot row j-2, panel column `lane`, completed
+      double lam_prev = 0.0;   // previous winner's multiplier for the pivot before it
+      uint64_t pay = 0;        // payload word `lane` of the previous winner (in flight)
+      uint64_t* prev_rec = a.rec;
+      bool to = false;
+
+      // Publishes the candidate record of step j from column 0 of x (and
+      // column 1 for the next-column value); the payload follows separately.
+      auto publish_header = [&](int j, const double (&lnew)[RPT], int& oq) -> uint64_t {
         double cv = -1.0;
         uint64_t ck = NOCAND;
-        if (active && part == qj) {
-          const double x = pv[sj];
-          cv = isnan(x) ? -0.5 : fabs(x);
-          ck = ((uint64_t)pos << 32) | (uint64_t)row;
-        }
-        wg_argmax(cv, ck, sv, sk);
-        // ---- publish ----
-        uint64_t* myrec = a.rec + ((long)jg * G + g) * RW;
-        if (cv >= -0.5 && (long)(ck & 0xFFFFFFFFull) == row && row < ni && valid) {
 #pragma unroll
-          for (int q = 0; q < CPT; ++q) store_agent(myrec + 2 + part * CPT + q, dbits(canon(pv[q])));
-        }
-        if (tid == 0) {
-          if (jg == 0 && wg_bad) {
-            store_agent(myrec + 1, BADKEY);
-          } else {
-            store_agent(myrec + 1, ck);
-          }
-          store_agent(myrec, dbits(cv));
-        }
-        // ---- gather headers, agree on the winner ----
-        double gv = -2.0;
-        uint64_t gk = NOCAND;
-        if (tid < G) {
-          // both header words are requested together: one round trip when ready
-          uint64_t* r = a.rec + ((long)jg * G + tid) * RW;
-          uint64_t key = load_agent(r + 1);
-          uint64_t vb = load_agent(r);
-          long spins = 0;
-          while (key == SENT || vb == SENT) {
-            if (++spins > kSpinLimit) { timed_out = true; break; }
-            __builtin_amdgcn_s_sleep(1);
-            if (key == SENT) key = load_agent(r + 1);
-            if (vb == SENT) vb = load_agent(r);
-          }
-          if (!timed_out) {
-            if (key == BADKEY) {
-              sflag = 2;
-            } else if (key != NOCAND) {
-              gv = bitsd(vb);
-              gk = key;
+        for (int q = 0; q < RPT; ++q) {
+          if (act[q]) {
+            const double v = cand_value(x[q][0]);
+            const uint64_t k = ((uint64_t)pos[q] << 32) | (uint64_t)row[q];
+            if (better(v, k, cv, ck)) {
+              cv = v;
+              ck = k;
             }
           }
-          if (timed_out) sflag = 3;
         }
-        wg_argmax(gv, gk, sv, sk);  // contains __syncthreads: sflag visible after it
-        if (sflag >= 2) {
-          if (tid == 0) store_agent_i32(a.status, sflag == 2 ? QRCP_ERR_NONFINITE : QRCP_ERR_TIMEOUT);
-          return;  // uniform
-        }
-        const long wrow = (long)(gk & 0xFFFFFFFFull);
-        const long wpos = (long)(gk >> 32);
-        const int wg = (int)(wrow / R);
-        uint64_t* wrec = a.rec + ((long)jg * G + wg) * RW;
-        // the winner's panel row: NB threads fetch one word each into LDS
-        if (tid < NB) sPiv[tid] = bitsd(poll(wrec + 2 + tid, timed_out));
-        __syncthreads();
-        double piv[CPT];
+        wave_argmax(cv, ck);
+        uint64_t* myrec = a.rec + ((long)j * G + g) * RW;
+        oq = -1;
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) piv[q] = sPiv[part * CPT + q];
-        const double pj = sPiv[jl];
-        if (tid == 0) {
-          sWin[jl] = wg;
+        for (int q = 0; q < RPT; ++q) {
+          if (act[q] && ck != NOCAND && (uint64_t)row[q] == (ck & 0xFFFFFFFFull)) {
+            oq = q;
+            store_agent(myrec + 2, canon(x[q][0]));
+            store_agent(myrec + 3, canon(lnew[q]));
+            store_agent(myrec + 4, canon(x[q][1]));
+            store_agent(myrec + 1, (j == 0 && wg_bad) ? BADKEY : ck);
+            store_agent(myrec, dbits(cv));
+          }
+        }
+        if (ck == NOCAND && lane == 0) {
+          store_agent(myrec + 2, 0);
+          store_agent(myrec + 3, 0);
+          store_agent(myrec + 4, 0);
+          store_agent(myrec + 1, (j == 0 && wg_bad) ? BADKEY : NOCAND);
+          store_agent(myrec, dbits(-1.0));
+        }
+        return ck;
+      };
+      // Payload of the candidate published for step j (owner lane, slot oq):
+      // multipliers for the panel columns before j, current values from j on.
+      auto publish_payload = [&](int j, int oq) {
+        uint64_t* myrec = a.rec + ((long)j * G + g) * RW + HW;
+        const int jl = j - p0;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          if (q == oq) {
+            const int lr = lane + 64 * q;
+            for (int c = 0; c < jl; ++c) store_agent(myrec + c, canon(sLr[lr][c]));
+#pragma unroll
+            for (int t = 0; t < NB; ++t)
+              if (jl + t < NB) store_agent(myrec + jl + t, canon(x[q][t]));
+          }
+        }
+      };
+
+      {
+        int oq;
+        publish_header(p0, lprev, oq);
+        publish_payload(p0, oq);
+      }
+      for (int jl = 0; jl < ns; ++jl) {
+        const int j = p0 + jl;
+        // ---- headers of step j ----
+        double bv = -2.0;
+        uint64_t bk = NOCAND;
+        double hx[GQ], hl[GQ], hr[GQ];
+        bool badseen = false;
+#pragma unroll
+        for (int qq = 0; qq < GQ; ++qq) {
+          hx[qq] = 0.0;
+          hl[qq] = 0.0;
+          hr[qq] = 0.0;
+          const int gg = lane + 64 * qq;
+          if (gg < G && !to) {
+            uint64_t* r = a.rec + ((long)j * G + gg) * RW;
+            uint64_t w[HW];
+#pragma unroll
+            for (int i = 0; i < HW; ++i) w[i] = load_agent(r + i);
+            long spins = 0;
+            for (;;) {
+              bool miss = false;
+#pragma unroll
+              for (int i = 0; i < HW; ++i) miss |= (w[i] == SENT);
+              if (!miss) break;
+              if (++spins > kSpinLimit) {
+                to = true;
+                break;
+              }
+              __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+              for (int i = 0; i < HW; ++i)
+                if (w[i] == SENT) w[i] = load_agent(r + i);
+            }
+            if (!to) {
+              if (w[1] == BADKEY) {
+                badseen = true;
+              } else if (w[1] != NOCAND) {
+                const double v = bitsd(w[0]);
+                if (better(v, w[1], bv, bk)) {
+                  bv = v;
+                  bk = w[1];
+                }
+              }
+              hx[qq] = bitsd(w[2]);
+              hl[qq] = bitsd(w[3]);
+              hr[qq] = bitsd(w[4]);
+            }
+          }
+        }
+        wave_argmax(bv, bk);
+        if (__any(to) || __any(badseen)) {
+          if (lane == 0) {
+            store_agent_i32(a.status, __any(to) ? QRCP_ERR_TIMEOUT : QRCP_ERR_NONFINITE);
+            sErr = 1;
+          }
+          break;
+        }
+        const long wrow = (long)(bk & 0xFFFFFFFFull);
+        const long wpos = (long)(bk >> 32);
+        const int wg = (int)(wrow / R), wl = wg & 63, wq = wg >> 6;
+        double sx = hx[0], sl = hl[0], sr = hr[0];
+#pragma unroll
+        for (int qq = 1; qq < GQ; ++qq)
+          if (qq == wq) {
+            sx = hx[qq];
+            sl = hl[qq];
+            sr = hr[qq];
+          }
+        const double pjj = rdlane_d(sx, wl), lam = rdlane_d(sl, wl), r1 = rdlane_d(sr, wl);
+
+        // ---- pivot row j-1, completed from its payload ----
+        double pcur = 0.0;
+        if (jl > 0) {
+          if (lane < NB) {
+            long spins = 0;
+            while (pay == SENT) {
+              if (++spins > kSpinLimit) {
+                to = true;
+                break;
+              }
+              __builtin_amdgcn_s_sleep(1);
+              pay = load_agent(prev_rec + HW + lane);
+            }
+          }
+          if (__any(to)) {
+            if (lane == 0) {
+              store_agent_i32(a.status, QRCP_ERR_TIMEOUT);
+              sErr = 1;
+            }
+            break;
+          }
+          const double raw = bitsd(pay);
+          if (lane < jl - 1) sL11[jl - 1][lane] = raw;
+          pcur = (lane >= jl && lane < NB) ? raw - lam_prev * pprev : 0.0;
+        }
+        // this winner's payload: requested now, used at the next step
+        uint64_t* wrec = a.rec + ((long)j * G + wg) * RW;
+        pay = (lane < NB) ? load_agent(wrec + HW + lane) : 0;
+        prev_rec = wrec;
+        if (lane == 0) {
           sRow[jl] = wrow;
           if (g == 0) {
-            a.ipiv[jg] = wpos;
-            a.jsk[jg] = wrow;
+            a.ipiv[j] = wpos;
+            a.jsk[j] = wrow;
           }
         }
-        // ---- swap bookkeeping and elimination ----
-        const double xj = __shfl(pv[sj], (lane & ~(TPR - 1)) + qj, 64);
-        if (active && row == wrow) {
-          active = false;
-        } else if (active) {
-          if (pos == jg) pos = wpos;
-          const double l = (pj != 0.0) ? xj / pj : 0.0;
+
+        // ---- elimination: next column now, the rest after the header ----
+        const double pj1 = r1 - lam * rdlane_d(pcur, jl + 1);   // U(j, j+1)
+        const double s1 = rdlane_d(pcur, jl + 1), s2 = rdlane_d(pcur, jl + 2);
+        double lnew[RPT];
 #pragma unroll
-          for (int q = 0; q < CPT; ++q) {
-            const int c = part * CPT + q;
-            if (c > jl) pv[q] -= l * piv[q];
+        for (int q = 0; q < RPT; ++q) {
+          lnew[q] = 0.0;
+          if (act[q] && row[q] == wrow) act[q] = false;
+          if (act[q]) {
+            if (pos[q] == j) pos[q] = wpos;
+            x[q][1] -= lprev[q] * s1;
+            x[q][2] -= lprev[q] * s2;
+            const double l = (pjj != 0.0) ? x[q][0] / pjj : 0.0;
+            x[q][1] -= l * pj1;
+            lnew[q] = l;
+            sLr[lane + 64 * q][jl] = l;
           }
-          if (part == qj) pv[sj] = l;
+        }
+        // shift: column j+1 becomes register 0
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+#pragma unroll
+          for (int t = 0; t < NB - 1; ++t) x[q][t] = x[q][t + 1];
+          x[q][NB - 1] = 0.0;
+        }
+        int oq = -1;
+        if (jl + 1 < ns) publish_header(j + 1, lnew, oq);
+        // previous pivot's contribution to the remaining panel columns
+#pragma unroll
+        for (int t = 2; t < NB - 1; ++t) {
+          const double s = rdlane_d(pcur, jl + 1 + t);
+#pragma unroll
+          for (int q = 0; q < RPT; ++q)
+            if (act[q]) x[q][t] -= lprev[q] * s;
+        }
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) lprev[q] = lnew[q];
+        pprev = pcur;
+        lam_prev = lam;
+        if (jl + 1 < ns) publish_payload(j + 1, oq);
+      }
+      // the last pivot row's multipliers (row ns-1 of L11)
+      if (!sErr) {
+        if (lane < NB) {
+          long spins = 0;
+          while (pay == SENT) {
+            if (++spins > kSpinLimit) {
+              to = true;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            pay = load_agent(prev_rec + HW + lane);
+          }
+        }
+        if (__any(to)) {
+          if (lane == 0) {
+            store_agent_i32(a.status, QRCP_ERR_TIMEOUT);
+            sErr = 1;
+          }
+        } else if (lane < ns - 1) {
+          sL11[ns - 1][lane] = bitsd(pay);
         }
       }
-    }
-    // uniform timeout check
-    __syncthreads();
-    if (timed_out) sflag = 3;
-    __syncthreads();
-    if (sflag == 3) {
-      if (tid == 0) store_agent_i32(a.status, QRCP_ERR_TIMEOUT);
-      return;
-    }
-    const int pend = min(p0 + NB, steps);
-    if (pend >= steps) break;   // no later pivot step needs the trailing columns
-    // ---- blocked trailing update of columns p0+NB .. d ----
-    // multipliers of my rows (pivot rows are no longer updated)
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) sLr[rl][part * CPT + q] = pv[q];
-    // L11 from the winners' records
-    for (int e = tid; e < NB * NB; e += NT) {
-      const int ar = e / NB, t = e % NB;
-      double v = 0.0;
-      if (t < ar) {
-        uint64_t* wrec = a.rec + ((long)(p0 + ar) * G + sWin[ar]) * RW;
-        v = bitsd(load_agent(wrec + 2 + t));
-      }
-      sL11[ar][t] = v;
+      for (int q = 0; q < RPT; ++q) sAct[lane + 64 * q] = act[q] ? 1 : 0;
     }
+    __syncthreads();
+    if (sErr) return;  // uniform
+    const int pend = p0 + ns;
+    if (pend >= steps) break;  // no later pivot step needs the trailing columns
+
+    // ---- blocked trailing update of columns pend .. d ----
     __threadfence();  // acquire: pivot rows' trailing values written by their owners
-    for (int c0 = p0 + NB; c0 < d; c0 += TCH) {
+    for (int c0 = pend; c0 < d; c0 += TCH) {
       const int cw = min(TCH, d - c0);
-      __syncthreads();
-      for (int e = tid; e < NB * cw; e += NT) {
-        const int ar = e / cw, c = e % cw;
-        sU[ar][c] = a.xw[sRow[ar] * (long)d + c0 + c];
+      if (tid < cw) {
+        double u[NB];
+#pragma unroll
+        for (int t = 0; t < NB; ++t) u[t] = a.xw[sRow[t] * (long)d + c0 + tid];
+#pragma unroll
+        for (int t = 1; t < NB; ++t)
+#pragma unroll
+          for (int s = 0; s < t; ++s) u[t] -= sL11[t][s] * u[s];
+#pragma unroll
+        for (int t = 0; t < NB; ++t) sU[t][tid] = u[t];
       }
       __syncthreads();
-      // U12 = L11^{-1} X(piv, chunk): one column per thread
-      for (int c = tid; c < cw; c += NT) {
-        for (int ar = 1; ar < NB; ++ar) {
-          double s = sU[ar][c];
-          for (int t = 0; t < ar; ++t) s -= sL11[ar][t] * sU[t][c];
-          sU[ar][c] = s;
+      // X(r, chunk) -= L(r, panel) U12: 16 x 16 blocks, D(i, j) in lane j + 16 (i % 4)
+      constexpr int NRB = R / 16;
+      const int ncb = (cw + 15) / 16;
+      for (int cb = wv; cb < ncb; cb += 4) {
+        const int col = c0 + cb * 16 + i16;
+        double old[NRB][4];
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int lr = rb * 16 + 4 * r + k4;
+            old[rb][r] = (sAct[lr] && col < d) ? a.xw[(row0 + lr) * d + col] : 0.0;
+          }
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb) {
+          dv4 acc = dv4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int s = 0; s < 8; ++s)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sLr[rb * 16 + i16][4 * s + k4],
+                                                       sU[4 * s + k4][cb * 16 + i16], acc, 0, 0,
+                                                       0);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int lr = rb * 16 + 4 * r + k4;
+            if (sAct[lr] && col < d) a.xw[(row0 + lr) * d + col] = old[rb][r] - acc[r];
+          }
         }
       }
       __syncthreads();
-      if (active) {
-        for (int c = part; c < cw; c += TPR) {
-          double x = xw[c0 + c];
-#pragma unroll 8
-          for (int t = 0; t < NB; ++t) x -= sLr[rl][t] * sU[t][c];
-          xw[c0 + c] = x;
-        }
-      }
     }
     __threadfence();  // release: my trailing values before the next records
     __syncthreads();
   }
   // positions of the rows that were never pivots
-  if (valid && active && part == 0 && pos < ni) a.jsk[pos] = row;
+  if (wv == 0) {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+      if (act[q] && pos[q] < ni) a.jsk[pos[q]] = row[q];
+  }
 }
 
-int pick_tpr(long ni) {
-  if ((ni + 63) / 64 <= kMaxGroups) return 4;
+int pick_rpt(long ni) {
+  static const int forced = [] {
+    const char* e = getenv("QRCP_LU_RPT");
+    return e ? atoi(e) : 0;
+  }();
+  if ((forced == 1 || forced == 2) && (ni + 64L * forced - 1) / (64L * forced) <= kMaxGroups)
+    return forced;
+  if (ni <= 64L * 64) return 1;
   if ((ni + 127) / 128 <= kMaxGroups) return 2;
-  if ((ni + 255) / 256 <= kMaxGroups) return 1;
   return 0;
 }
 
 }  // namespace
 
 size_t lu_records_bytes(int d, i64 ni) {
-  const int tpr = pick_tpr(ni);
-  if (!tpr) return 0;
-  const long G = (ni + (NT / tpr) - 1) / (NT / tpr);
+  const int rpt = pick_rpt(ni);
+  if (!rpt) return 0;
+  const long G = (ni + 64L * rpt - 1) / (64L * rpt);
   const long steps = std::min((long)d, (long)ni);
   return (size_t)steps * G * RW * sizeof(uint64_t);
 }
@@ -315,18 +485,15 @@ size_t lu_records_bytes(int d, i64 ni) {
 int launch_lu_pivots(const double* Msk, int d, i64 ni, i64 ld, double* Xw, uint64_t* rec,
                      size_t rec_bytes, i64* ipiv, i64* jsk, int* status_dev, hipStream_t st) {
   if (ni <= 0 || d <= 0) return QRCP_OK;
-  const int tpr = pick_tpr(ni);
-  if (!tpr) return QRCP_ERR_UNSUPPORTED;
+  const int rpt = pick_rpt(ni);
+  if (!rpt) return QRCP_ERR_UNSUPPORTED;
   const size_t need = lu_records_bytes(d, ni);
   if (need > rec_bytes) return QRCP_ERR_WORKSPACE;
-  const int R = NT / tpr;
-  const int G = (int)((ni + R - 1) / R);
+  const int G = (int)((ni + 64L * rpt - 1) / (64L * rpt));
   QRCP_TRY(launch_fill_u64(rec, (i64)(need / sizeof(uint64_t)), SENT, st));
   LuArgs args{Msk, (long)ld, d, (long)ni, Xw, rec, (long*)ipiv, (long*)jsk, status_dev};
   void* params[] = {&args};
-  const void* fn = tpr == 4 ? (const void*)lu_pivots_kernel<4>
-                 : tpr == 2 ? (const void*)lu_pivots_kernel<2>
-                            : (const void*)lu_pivots_kernel<1>;
+  const void* fn = rpt == 1 ? (const void*)lu_pivots_kernel<1> : (const void*)lu_pivots_kernel<2>;
   QRCP_TRY(launch_resident(fn, dim3(G), dim3(NT), params, 0, st));
   return QRCP_OK;
 }
