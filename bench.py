@@ -81,7 +81,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "the method's multi-GPU sharding is described in DESIGN.md but not built.",
+              "a multi-GPU sharding of the method is not built.",
               file=sys.stderr)
         sys.exit(2)
 

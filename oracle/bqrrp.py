@@ -11,8 +11,8 @@ step where a step *is* that primitive.  Every function names the passage of
 the paper (arXiv 2507.00976, "Anatomy of High-Performance Column-Pivoted QR
 Decomposition") it follows.  Indices are 0-based, as in the paper (Sec. 1.3).
 
-Readings of the paper where it is silent or ambiguous are listed in the design doc
-("Readings of the paper"); the ones that shape this file are repeated inline.
+Where the paper is silent or ambiguous, the reading taken is stated inline
+at the step it shapes.
 """
 from __future__ import annotations
 

@@ -99,8 +99,9 @@ __device__ __forceinline__ double cand_value(double x) { return isnan(x) ? -0.5 
 template <int RPT>
 __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
   constexpr int R = 64 * RPT;
-  __shared__ double sU[NB][TCH];         // U12 chunk
-  __shared__ double sLr[R][NB + 1];      // multipliers of this workgroup's rows
+  // row strides padded so that the matrix-core operand reads are free of bank conflicts
+  __shared__ double sU[NB][TCH + 16];    // U12 chunk
+  __shared__ double sLr[R][NB + 2];      // multipliers of this workgroup's rows
   __shared__ double sL11[NB][NB + 1];    // multipliers of the panel's pivot rows
   __shared__ long sRow[NB];              // the panel's pivot rows
   __shared__ int sAct[R];

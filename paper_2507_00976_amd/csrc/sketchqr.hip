@@ -23,6 +23,7 @@ int launch_set_identity(double* dst, i64 ld, i64 n, hipStream_t st);
 namespace {
 constexpr int NT = 256;
 constexpr int VCH = 64;  // rows of V_p staged per pass when applying
+constexpr int VLD = VCH + 1;  // their LDS stride (odd: no bank conflicts)
 
 struct HeadArgs {
   const double* B;
@@ -42,7 +43,8 @@ typedef double hv4 __attribute__((ext_vector_type(4)));
 // W(32 x 32) = V_p^T C over rows [p0, d): V_p staged from global in row chunks,
 // C in LDS.  Wave w owns the 16 x 16 block (w & 1, w >> 1) of W; FP64 MFMA.
 // Then C -= V_p W' with W' = T_p^T W.  PW = 32 only (the MFMA path).
-__device__ void apply_panel_mfma(double* sC, int d, const double* V, int p0, int pc, const double* Tg,
+__device__ void apply_panel_mfma(double* sC, int d, int ldc, const double* V, int p0, int pc,
+                                 const double* Tg,
                                  double* sV, double* sW, double* sT, double* sW2) {
   constexpr int PW = 32;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -54,14 +56,14 @@ __device__ void apply_panel_mfma(double* sC, int d, const double* V, int p0, int
     __syncthreads();
     for (int e = tid; e < VCH * PW; e += NT) {
       const int rr = e % VCH, aa = e / VCH;
-      sV[aa * VCH + rr] = (rr < rows && aa < pc) ? V[(r0 + rr) + (long)(p0 + aa) * d] : 0.0;
+      sV[aa * VLD + rr] = (rr < rows && aa < pc) ? V[(r0 + rr) + (long)(p0 + aa) * d] : 0.0;
     }
     __syncthreads();
     for (int k0 = 0; k0 < rows; k0 += 4) {
       const int kr = k0 + (lane >> 4);
       // src0 = A(i, k) = V(r0 + k, 16 bi + i); src1 = B(k, j) = C(r0 + k, 16 bj + j)
-      const double a = (kr < rows) ? sV[(16 * bi + (lane & 15)) * VCH + kr] : 0.0;
-      const double b = (kr < rows) ? sC[(16 * bj + (lane & 15)) * d + r0 + kr] : 0.0;
+      const double a = (kr < rows) ? sV[(16 * bi + (lane & 15)) * VLD + kr] : 0.0;
+      const double b = (kr < rows) ? sC[(16 * bj + (lane & 15)) * ldc + r0 + kr] : 0.0;
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
     }
   }
@@ -82,7 +84,7 @@ __device__ void apply_panel_mfma(double* sC, int d, const double* V, int p0, int
     __syncthreads();
     for (int e = tid; e < VCH * PW; e += NT) {
       const int rr = e % VCH, aa = e / VCH;
-      sV[aa * VCH + rr] = (rr < rows && aa < pc) ? V[(r0 + rr) + (long)(p0 + aa) * d] : 0.0;
+      sV[aa * VLD + rr] = (rr < rows && aa < pc) ? V[(r0 + rr) + (long)(p0 + aa) * d] : 0.0;
     }
     __syncthreads();
     const int nrb = (rows + 15) / 16;
@@ -92,14 +94,14 @@ __device__ void apply_panel_mfma(double* sC, int d, const double* V, int p0, int
       for (int k0 = 0; k0 < PW; k0 += 4) {
         const int kr = k0 + (lane >> 4);
         // src0 = A(i, k) = V(r0 + 16 rb + i, k), src1 = B(k, j) = W'(k, 16 cb + j)
-        const double a = sV[kr * VCH + 16 * rb + (lane & 15)];
+        const double a = sV[kr * VLD + 16 * rb + (lane & 15)];
         const double b = sW2[kr * PW + 16 * cb + (lane & 15)];
         c4 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c4, 0, 0, 0);
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = 16 * rb + 4 * r + (lane >> 4), j = 16 * cb + (lane & 15);
-        if (i < rows) sC[j * d + r0 + i] -= c4[r];
+        if (i < rows) sC[j * ldc + r0 + i] -= c4[r];
       }
     }
   }
@@ -110,9 +112,10 @@ template <int PW>
 __global__ __launch_bounds__(NT) void sketch_head_kernel(HeadArgs a) {
   extern __shared__ double smem[];
   const int d = a.d, dh = a.dh;
+  const int ldc = d + 1;                   // odd column stride: no LDS bank conflicts across columns
   double* sC = smem;                       // PW columns x d rows
-  double* sV = sC + (long)PW * d;          // VCH x PW staging
-  double* sW = sV + VCH * PW;              // PW x PW
+  double* sV = sC + (long)PW * ldc;        // VCH x PW staging
+  double* sW = sV + VLD * PW;              // PW x PW
   double* sT = sW + PW * PW;               // PW x PW
   double* sPart = sT + PW * PW;            // max(PW x PW, NT) scratch
   __shared__ double sTau[PW];
@@ -128,7 +131,7 @@ __global__ __launch_bounds__(NT) void sketch_head_kernel(HeadArgs a) {
 
   for (int e = tid; e < PW * d; e += NT) {
     const int c = e / d, r = e % d;
-    sC[c * d + r] = (c < ncol) ? a.B[r + (long)(c0 + c) * a.ldb] : 0.0;
+    sC[c * ldc + r] = (c < ncol) ? a.B[r + (long)(c0 + c) * a.ldb] : 0.0;
   }
   if (tid == 0) sbad = 0;
   __syncthreads();
@@ -151,7 +154,7 @@ __global__ __launch_bounds__(NT) void sketch_head_kernel(HeadArgs a) {
     }
     __threadfence();
     if constexpr (PW == 32) {
-      apply_panel_mfma(sC, d, a.V, p0, pc, a.T + (long)p * PW * PW, sV, sW, sT, sPart);
+      apply_panel_mfma(sC, d, ldc, a.V, p0, pc, a.T + (long)p * PW * PW, sV, sW, sT, sPart);
     } else {
       for (int e = tid; e < PW * PW; e += NT) sT[e] = a.T[(long)p * PW * PW + e];
       for (int e = tid; e < PW * PW; e += NT) sW[e] = 0.0;
@@ -160,13 +163,13 @@ __global__ __launch_bounds__(NT) void sketch_head_kernel(HeadArgs a) {
         const int rows = min(VCH, d - r0);
         for (int e = tid; e < VCH * PW; e += NT) {
           const int rr = e % VCH, aa = e / VCH;
-          sV[aa * VCH + rr] = (rr < rows && aa < pc) ? a.V[(r0 + rr) + (long)(p0 + aa) * d] : 0.0;
+          sV[aa * VLD + rr] = (rr < rows && aa < pc) ? a.V[(r0 + rr) + (long)(p0 + aa) * d] : 0.0;
         }
         __syncthreads();
         for (int e = tid; e < PW * PW; e += NT) {
           const int aa = e / PW, c = e % PW;
           double s = 0.0;
-          for (int rr = 0; rr < rows; ++rr) s += sV[aa * VCH + rr] * sC[c * d + r0 + rr];
+          for (int rr = 0; rr < rows; ++rr) s += sV[aa * VLD + rr] * sC[c * ldc + r0 + rr];
           sW[aa * PW + c] += s;
         }
         __syncthreads();
@@ -182,15 +185,15 @@ __global__ __launch_bounds__(NT) void sketch_head_kernel(HeadArgs a) {
         const int rows = min(VCH, d - r0);
         for (int e = tid; e < VCH * PW; e += NT) {
           const int rr = e % VCH, aa = e / VCH;
-          sV[aa * VCH + rr] = (rr < rows && aa < pc) ? a.V[(r0 + rr) + (long)(p0 + aa) * d] : 0.0;
+          sV[aa * VLD + rr] = (rr < rows && aa < pc) ? a.V[(r0 + rr) + (long)(p0 + aa) * d] : 0.0;
         }
         __syncthreads();
         for (int e = tid; e < VCH * PW; e += NT) {
           const int rr = e % VCH, c = e / VCH;
           if (rr < rows) {
             double s = 0.0;
-            for (int aa = 0; aa < pc; ++aa) s += sV[aa * VCH + rr] * sPart[aa * PW + c];
-            sC[c * d + r0 + rr] -= s;
+            for (int aa = 0; aa < pc; ++aa) s += sV[aa * VLD + rr] * sPart[aa * PW + c];
+            sC[c * ldc + r0 + rr] -= s;
           }
         }
         __syncthreads();
@@ -205,11 +208,11 @@ __global__ __launch_bounds__(NT) void sketch_head_kernel(HeadArgs a) {
   // Column jj itself is scaled to v when the panel is published.
   for (int jj = 0; jj < ncol; ++jj) {
     const int rj = c0 + jj;
-    const double* xj = sC + jj * d;
+    const double* xj = sC + jj * ldc;
     {
       double s = 0.0;
       if (cg >= jj && cg < ncol)
-        for (int r = rj + 1 + rg; r < d; r += RG) s += xj[r] * sC[cg * d + r];
+        for (int r = rj + 1 + rg; r < d; r += RG) s += xj[r] * sC[cg * ldc + r];
       sPart[rg * PW + cg] = s;
     }
     __syncthreads();
@@ -229,11 +232,11 @@ __global__ __launch_bounds__(NT) void sketch_head_kernel(HeadArgs a) {
       inv = alpha - beta;
     }
     if (tau != 0.0 && cg > jj && cg < ncol) {
-      const double wc = sC[cg * d + rj] + sW[cg] / inv;
+      const double wc = sC[cg * ldc + rj] + sW[cg] / inv;
       const double f = tau * wc;
-      if (rg == 0) sC[cg * d + rj] -= f;
+      if (rg == 0) sC[cg * ldc + rj] -= f;
       const double fv = f / inv;
-      for (int r = rj + 1 + rg; r < d; r += RG) sC[cg * d + r] -= fv * xj[r];
+      for (int r = rj + 1 + rg; r < d; r += RG) sC[cg * ldc + r] -= fv * xj[r];
     }
     if (tid == 0) {
       sTau[jj] = tau;
@@ -249,9 +252,9 @@ __global__ __launch_bounds__(NT) void sketch_head_kernel(HeadArgs a) {
     const int c = e / d, r = e % d;
     if (c < ncol) {
       const int rc = c0 + c;
-      double v = sC[c * d + r];
+      double v = sC[c * ldc + r];
       if (r > rc) v = (sInv[c] != 0.0) ? v / sInv[c] : 0.0;
-      sC[c * d + r] = (r == rc) ? 1.0 : v;   // keep the scaled vector for T below
+      sC[c * ldc + r] = (r == rc) ? 1.0 : v;   // keep the scaled vector for T below
       a.V[r + (long)rc * d] = (r < rc) ? 0.0 : (r == rc ? 1.0 : v);
       if (r < rc) a.R[r + (long)rc * a.ldr] = v;
       else if (r > rc) a.R[r + (long)rc * a.ldr] = 0.0;
@@ -265,8 +268,8 @@ __global__ __launch_bounds__(NT) void sketch_head_kernel(HeadArgs a) {
     if (i < j && j < ncol) {
       const int rjj = c0 + j;
       // V(:, i)^T V(:, j): rows >= rjj (V(r, j) = 0 above rjj, 1 at rjj)
-      s = sC[i * d + rjj];
-      for (int r = rjj + 1; r < d; ++r) s += sC[i * d + r] * sC[j * d + r];
+      s = sC[i * ldc + rjj];
+      for (int r = rjj + 1; r < d; ++r) s += sC[i * ldc + r] * sC[j * ldc + r];
     }
     sW[i * PW + j] = s;  // G(i, j) for i < j
   }
@@ -341,7 +344,7 @@ int run_sketch_qr(const double* B, int d, i64 ni, i64 ldb, double* R, i64 ldr, v
   QRCP_TRY(launch_fill_u64((uint64_t*)flags, (np + 1) / 2, 0ull, st));
   HeadArgs args{B, (long)ldb, d, dh, pw, R, (long)ldr, V, tau, Tp, flags, status_dev};
   void* params[] = {&args};
-  const size_t smem = ((size_t)pw * d + 64 * pw + 2 * pw * pw + std::max<size_t>((size_t)pw * pw, NT)) * 8;
+  const size_t smem = ((size_t)pw * (d + 1) + VLD * pw + 2 * pw * pw + std::max<size_t>((size_t)pw * pw, NT)) * 8;
   const void* fn = pw == 32 ? (const void*)sketch_head_kernel<32>
                  : pw == 16 ? (const void*)sketch_head_kernel<16>
                             : (const void*)sketch_head_kernel<8>;
