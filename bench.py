@@ -64,6 +64,215 @@ def sampled_residual(torch, A0, A, jpiv, tau, rank, cols):
     return float((torch.linalg.norm(ref - x, dim=0) / torch.linalg.norm(ref, dim=0)).max())
 
 
+def apply_q(torch, A, tau, rank, X, nb=256):
+    """X <- Q X with Q = H_0 ... H_{rank-1} from the stored reflectors (test code, torch)."""
+    for s in reversed(range(0, rank, nb)):
+        k = min(nb, rank - s)
+        y = torch.tril(A[s:, s:s + k], -1)
+        y[:k, :k] += torch.eye(k, dtype=A.dtype, device=A.device)
+        t = tau[s:s + k]
+        live = t != 0
+        y[:, ~live] = 0.0
+        t_inv = torch.diag(torch.where(live, 1.0 / torch.where(live, t, 1.0), 1.0)) + \
+            torch.triu(y.t() @ y, 1)
+        tm = torch.linalg.inv(t_inv)
+        tm[~live, :] = 0.0
+        tm[:, ~live] = 0.0
+        X[s:] -= y @ (tm @ (y.t() @ X[s:]))
+    return X
+
+
+def full_checks(torch, A0, A, jpiv, tau, rank):
+    """||A P - Q R||_F / ||A||_F and ||Q^T Q - I||_F over the first n columns of Q."""
+    m, n = A.shape
+    x = torch.zeros(m, n, dtype=A.dtype, device=A.device)
+    x[:rank] = torch.triu(A[:rank])
+    if rank < n:
+        x[rank:, rank:] = A[rank:, rank:]   # the residual block stays in place
+    apply_q(torch, A, tau, rank, x)
+    res = float(torch.linalg.norm(A0[:, jpiv] - x) / torch.linalg.norm(A0))
+    del x
+    q = torch.zeros(m, n, dtype=A.dtype, device=A.device)
+    q[:n, :n] = torch.eye(n, dtype=A.dtype, device=A.device)
+    apply_q(torch, A, tau, rank, q)
+    orth = float(torch.linalg.norm(q.t() @ q - torch.eye(n, dtype=A.dtype, device=A.device)))
+    del q
+    return res, orth
+
+
+def run_precision_variants(args, torch, qrcp, WD):
+    """Tall 65536 x 8192, sigma_i geometric 1 -> 1e-14: FP64, BF16 sketch, BF16 sketch + FP32
+    trailing update; residual, orthogonality, |R_kk|/sigma_k and pivot agreement with FP64."""
+    dev = torch.device("cuda:0")
+    m, n, b = args.m or 65536, args.n if args.n != 16384 else 8192, args.block
+    d = int(math.ceil(args.gamma * b - 1e-12))
+    sigma = WD.geometric_spectrum(n, 1e-14)
+    A0 = WD.usv(m, n, sigma, args.seed, dev)
+    A = qrcp.colmajor(A0.clone())
+    variants = [("fp64", {}), ("bf16_sketch", {"sketch_precision": 1, "cholqr_passes": 2}),
+                ("bf16_sketch_fp32_trailing",
+                 {"sketch_precision": 1, "trailing_precision": 1, "cholqr_passes": 2})]
+    out = {"metric": "QRCP precision variants 65536x8192", "unit": "GFLOP/s", "n_gpus": 1,
+           "higher_is_better": True, "data": "synthetic", "dtype": "f64",
+           "config": {"workload": f"qrcp {m}x{n} sigma geometric 1..1e-14 b={b} d={d}",
+                      "m": m, "n": n, "block_size": b, "sketch_rows": d}, "variants": {}}
+    ref_j = None
+    sig = sigma.to(dev)
+    for name, opts in variants:
+        ws = torch.empty(qrcp.workspace_size(m, n, b, args.gamma, **opts), dtype=torch.uint8,
+                         device=dev)
+        A.copy_(A0)
+        qrcp.factor(A, b, args.gamma, 42, 0.0, workspace=ws, **opts)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(max(args.steps, 1)):
+            A.copy_(A0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, jpiv, tau, rank = qrcp.factor(A, b, args.gamma, 42, 0.0, workspace=ws, **opts)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        del ws
+        dt = min(ts)
+        res, orth = full_checks(torch, A0, A, jpiv, tau, rank)
+        ratio = torch.abs(torch.diagonal(A)[:rank]) / sig[:rank]
+        agree = None if ref_j is None else float((jpiv == ref_j).double().mean())
+        if ref_j is None:
+            ref_j = jpiv.clone()
+        rec = {"ms": round(dt * 1e3, 2), "gflops": round(canonical_flops(m, n) / dt / 1e9, 1),
+               "rank": rank, "residual": res, "orthogonality": orth,
+               "rkk_over_sigma": {"min": float(ratio.min()), "median": float(ratio.median()),
+                                  "max": float(ratio.max())},
+               "pivot_agreement_with_fp64": agree, "options": opts}
+        out["variants"][name] = rec
+        log(f"{name}: {dt * 1e3:.1f} ms, res {res:.2e}, orth {orth:.2e}, "
+            f"|Rkk|/sigma_k in [{rec['rkk_over_sigma']['min']:.3g}, "
+            f"{rec['rkk_over_sigma']['max']:.3g}], pivots vs fp64 {agree}")
+    out["value"] = out["variants"]["fp64"]["gflops"]
+    print(json.dumps(out), flush=True)
+
+
+def run_lowrank(args, torch, qrcp, WD):
+    """32768^2 = rank-4096 Gaussian product + 1e-12 noise, b = 512, d = 640, tol = 1e-10:
+    detected rank, runtime, truncated-canonical GFLOP/s."""
+    dev = torch.device("cuda:0")
+    m = n = args.m or 32768
+    r, b, tol = 4096, 512, 1e-10
+    d = int(math.ceil(args.gamma * b - 1e-12))
+    A0 = WD.lowrank(m, n, r, 1e-12, args.seed, dev)
+    A = qrcp.colmajor(A0.clone())
+    ws = torch.empty(qrcp.workspace_size(m, n, b, args.gamma), dtype=torch.uint8, device=dev)
+    A.copy_(A0)
+    qrcp.factor(A, b, args.gamma, 42, tol, workspace=ws)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(max(args.steps, 1)):
+        A.copy_(A0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, jpiv, tau, rank = qrcp.factor(A, b, args.gamma, 42, tol, workspace=ws)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    dt = min(ts)
+    del ws
+    fl = truncated_flops(m, n, rank)
+    check = sampled_residual(torch, A0, A, jpiv, tau, rank,
+                             torch.tensor([0, 1, rank // 2, rank - 1], device=dev))
+    out = {"metric": "QRCP rank detection 32768^2 rank-4096 + 1e-12 noise", "unit": "GFLOP/s",
+           "value": round(fl / dt / 1e9, 1), "n_gpus": 1, "higher_is_better": True,
+           "ms": round(dt * 1e3, 2), "rank": rank, "rank_expected": r,
+           "sampled_residual_first_rank_columns": check,
+           "canonical_gflops_full": round(canonical_flops(m, n) / dt / 1e9, 1),
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"qrcp {m}x{n} rank {r} + 1e-12 N, b={b} d={d} tol={tol}",
+                      "m": m, "n": n, "block_size": b, "sketch_rows": d, "tol": tol}}
+    log(f"lowrank: {dt * 1e3:.1f} ms, rank {rank} (expected {r}), "
+        f"{fl / dt / 1e9:.1f} truncated GFLOP/s, sampled residual {check:.2e}")
+    print(json.dumps(out), flush=True)
+
+
+def run_serving(args, torch, qrcp, WD):
+    """Poisson stream of independent requests: m log-uniform in [256, 4096], n log-uniform in
+    [64, min(m, 1024)], b = min(64, n), d = ceil(1.25 b), spectrum geometric / (i+1)^-1 /
+    exact rank n/2 (tol 1e-13), served by the library's request server."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(args.seed)
+    nreq = args.requests
+    shapes = []
+    for i in range(nreq):
+        m = int(np.exp(rng.uniform(np.log(256), np.log(4096))))
+        n = int(np.exp(rng.uniform(np.log(64), np.log(min(m, 1024)))))
+        shapes.append((m, n, i % 3))
+    t0 = time.perf_counter()
+    mats = []
+    for i, (m, n, kind) in enumerate(shapes):
+        if kind == 0:
+            sig = WD.geometric_spectrum(n, 1e-10)
+        else:
+            sig = 1.0 / (torch.arange(n, dtype=torch.float64) + 1.0)
+            if kind == 2:
+                sig[n // 2:] = 0.0
+        mats.append(WD.usv(m, n, sig, args.seed + 1 + i, dev))
+    torch.cuda.synchronize()
+    log(f"generated {nreq} requests in {time.perf_counter() - t0:.1f}s")
+    pristine = [x.clone() for x in mats]
+    flops = [canonical_flops(m, n) for m, n, _ in shapes]
+
+    def submit_all(srv, order_times=None):
+        tickets, arrive = [], []
+        tstart = time.perf_counter()
+        done = {}
+        pending = []
+        for i, (m, n, kind) in enumerate(shapes):
+            if order_times is not None:
+                while time.perf_counter() - tstart < order_times[i]:
+                    for t in list(pending):
+                        r = srv.poll(t)
+                        if r is not None:
+                            done[t] = r
+                            pending.remove(t)
+                    time.sleep(0.0002)
+            mats[i].copy_(pristine[i])
+            b = min(64, n)
+            tol = 1e-13 if kind == 2 else 0.0
+            t = srv.submit(mats[i], b, 1.25, 42, tol)
+            tickets.append(t)
+            pending.append(t)
+        for t in pending:
+            done[t] = srv.wait(t)
+        wall = time.perf_counter() - tstart
+        res = [done[t] for t in tickets]
+        return wall, res
+
+    with qrcp.Server(slots=args.slots) as srv:
+        wall, res = submit_all(srv)          # closed loop: everything queued at once
+        cap = nreq / wall
+        log(f"closed loop: {nreq} requests in {wall:.2f}s = {cap:.1f} req/s, "
+            f"{sum(flops) / wall / 1e9:.1f} GFLOP/s")
+        lam = args.load * cap
+        gaps = rng.exponential(1.0 / lam, nreq)
+        times = np.cumsum(gaps) - gaps[0]
+        wall, res = submit_all(srv, times)
+    lat = np.array([r[4]["end_ms"] - r[4]["submit_ms"] for r in res])
+    ranks_ok = all(r[3] == (shapes[i][1] // 2 if shapes[i][2] == 2 else shapes[i][1])
+                   for i, r in enumerate(res))
+    out = {"metric": "QRCP serving req/s + p99 latency", "value": round(nreq / wall, 2),
+           "unit": "req/s", "n_gpus": 1, "higher_is_better": True,
+           "p50_ms": round(float(np.percentile(lat, 50)), 3),
+           "p99_ms": round(float(np.percentile(lat, 99)), 3),
+           "mean_ms": round(float(lat.mean()), 3),
+           "closed_loop_req_s": round(cap, 2), "offered_req_s": round(lam, 2),
+           "aggregate_gflops": round(sum(flops) / wall / 1e9, 1), "ranks_as_expected": ranks_ok,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{nreq} requests, m in [256,4096], n in [64,min(m,1024)] "
+                                  f"log-uniform, b=min(64,n), d=ceil(1.25b), Poisson arrivals at "
+                                  f"{args.load}x closed-loop capacity", "slots": args.slots}}
+    log(f"open loop at {lam:.1f} req/s offered: {nreq / wall:.1f} req/s, p50 {out['p50_ms']} ms, "
+        f"p99 {out['p99_ms']} ms")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +286,16 @@ def main():
     ap.add_argument("--no-geqrf", action="store_true")
     ap.add_argument("--breakdown", action="store_true", help="extra run timing every stage")
     ap.add_argument("--context", action="store_true", help="also time torch.geqrf (rocSOLVER)")
+    ap.add_argument("--workload", choices=["headline", "precision", "lowrank", "serving"],
+                    default="headline",
+                    help="headline: 16384^2 (default); precision: 65536x8192 FP64 / BF16-sketch / "
+                         "FP32-trailing variants; lowrank: 32768^2 rank-4096 detection; serving: "
+                         "Poisson stream of mixed-shape requests through the request server")
+    ap.add_argument("--requests", type=int, default=1000, help="serving: number of requests")
+    ap.add_argument("--slots", type=int, default=4, help="serving: concurrent requests")
+    ap.add_argument("--load", type=float, default=0.8,
+                    help="serving: offered rate as a fraction of the closed-loop capacity")
+    ap.add_argument("--m", type=int, default=0, help="rows (precision/lowrank workloads)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -90,6 +309,15 @@ def main():
 
     from paper_2507_00976_amd import qrcp
     from workloads import device as WD
+
+    if args.workload == "precision":
+        return run_precision_variants(args, torch, qrcp, WD)
+    if args.workload == "serving":
+        return run_serving(args, torch, qrcp, WD)
+    if args.workload == "lowrank":
+        if args.block == 256:
+            args.block = 512
+        return run_lowrank(args, torch, qrcp, WD)
 
     dev = torch.device("cuda:0")
     m = n = args.n

@@ -172,6 +172,66 @@ int qrcp_sketch_update(double* Rsk, int64_t d, int64_t b, int64_t nt, int64_t ld
                        void* workspace, size_t workspace_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Request server: many independent factorizations of mixed shapes in flight
+ * on one GPU (the paper's method applied per request; continuous admission).
+ *
+ * Worker threads (`slots`, each with its own HIP stream and cached workspace)
+ * take requests from one FIFO queue as soon as they can be admitted: the
+ * workers' workspaces together stay within `hbm_budget` bytes of device
+ * memory, and the cross-workgroup-waiting kernels of the running requests fit
+ * the device's compute units together.  Requests that arrive while others run
+ * start as soon as a slot and memory free up; their kernels overlap on the
+ * device.  A request computes exactly what qrcp_factor computes on the same
+ * arguments (bitwise: the same kernels in the same order).
+ * ---------------------------------------------------------------------- */
+typedef struct qrcp_server qrcp_server;
+
+typedef struct qrcp_server_cfg {
+  int32_t struct_size; /* sizeof(qrcp_server_cfg)                                */
+  int32_t slots;       /* worker threads / streams, 1..64 (0 = 4)                  */
+  int64_t hbm_budget;  /* bytes of workspace the server may hold (0 = 80% of the
+                          device memory free at creation)                         */
+  int32_t device;      /* HIP device ordinal                                      */
+} qrcp_server_cfg;
+
+typedef struct qrcp_request {
+  int32_t struct_size;   /* sizeof(qrcp_request)                                  */
+  int64_t m, n, lda;     /* as qrcp_factor                                        */
+  int64_t block_size;
+  double sketch_factor;
+  uint64_t seed;
+  double tol;
+  double* A;             /* DEVICE, caller-owned until the request completes      */
+  int64_t* jpiv;         /* DEVICE out, n                                         */
+  double* tau;           /* DEVICE out, min(m, n)                                 */
+  qrcp_opts opts;        /* struct_size = 0 selects the defaults                  */
+} qrcp_request;
+
+typedef struct qrcp_result {
+  int32_t struct_size;
+  int32_t status;        /* qrcp_factor's return value                            */
+  int64_t rank;
+  double submit_ms;      /* server clock: ms since qrcp_server_create             */
+  double start_ms;       /* admitted and started                                  */
+  double end_ms;         /* results final in device memory                        */
+} qrcp_result;
+
+/* NULL on failure (bad config, no device). */
+qrcp_server* qrcp_server_create(const qrcp_server_cfg* cfg);
+/* Queues a request; *ticket identifies it.  -i: i-th argument illegal;
+ * QRCP_ERR_UNSUPPORTED if it can never be admitted (m < n, workspace above the
+ * budget, resident grid above the device). */
+int qrcp_server_submit(qrcp_server* s, const qrcp_request* req, uint64_t* ticket);
+/* 0 = done (*out filled, ticket released), 1 = pending, -2 = unknown ticket. */
+int qrcp_server_poll(qrcp_server* s, uint64_t ticket, qrcp_result* out);
+/* Blocks until the request is done; 0, or -2 for an unknown ticket. */
+int qrcp_server_wait(qrcp_server* s, uint64_t ticket, qrcp_result* out);
+/* Requests submitted and not yet done. */
+int qrcp_server_pending(qrcp_server* s);
+/* Finishes every queued request, then frees the server. */
+void qrcp_server_destroy(qrcp_server* s);
+
+/* ------------------------------------------------------------------------
  * Stage timing (instrumentation, not part of the method).  mode 0 = off,
  * 1 = time only the trailing-update product C -= Y W (the dominant kernel),
  * 2 = time every stage of the loop.  Enabling clears earlier records.  HIP

@@ -87,4 +87,9 @@ int launch_final_permute(double* A, i64 lda, i64 m, i64 l, i64 n, const i64* phy
 int launch_jpiv_out(const i64* J, i64 n, i64 base, i64* out, hipStream_t st);
 int launch_iota(i64* x, i64 n, hipStream_t st);
 
+// Workgroups of the kernels whose workgroups wait on each other (all must be
+// resident at once): pivot selection on n_i sketch columns, sketch-QR head.
+int lu_resident_groups(i64 ni);
+int sketch_head_groups(int d, i64 ni);
+
 }  // namespace qrcp

@@ -69,18 +69,51 @@ __device__ __forceinline__ bool better(double va, uint64_t ka, double vb, uint64
   return va > vb || (va == vb && ka < kb);
 }
 
-// Wave-wide argmax of (v, key); every lane gets the result.
+__device__ __forceinline__ double rdlane_d(double v, int l);
+__device__ __forceinline__ uint64_t rdlane_u64(uint64_t v, int l) {
+  const int lo = __builtin_amdgcn_readlane((int)(v & 0xFFFFFFFFull), l);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// One exchange step of the argmax inside rows of 16 lanes: DPP moves (no LDS).
+template <int CTRL>
+__device__ __forceinline__ void argmax_dpp(double& v, uint64_t& key) {
+  const long long vb = __double_as_longlong(v);
+  const int vlo = __builtin_amdgcn_update_dpp((int)vb, (int)vb, CTRL, 0xF, 0xF, false);
+  const int vhi = __builtin_amdgcn_update_dpp((int)(vb >> 32), (int)(vb >> 32), CTRL, 0xF, 0xF, false);
+  const int klo = __builtin_amdgcn_update_dpp((int)key, (int)key, CTRL, 0xF, 0xF, false);
+  const int khi = __builtin_amdgcn_update_dpp((int)(key >> 32), (int)(key >> 32), CTRL, 0xF, 0xF, false);
+  const double ov = __longlong_as_double(((long long)vhi << 32) | (uint32_t)vlo);
+  const uint64_t ok = ((uint64_t)(uint32_t)khi << 32) | (uint32_t)klo;
+  if (better(ov, ok, v, key)) {
+    v = ov;
+    key = ok;
+  }
+}
+
+// Wave-wide argmax of (v, key); every lane gets the result.  Lanes exchange
+// with lane^1, lane^2 (quad permutations), then the mirrored lane of the half
+// row and of the row, so every lane of a 16-lane row holds the row's best;
+// the four rows are combined through scalar reads.
 __device__ __forceinline__ void wave_argmax(double& v, uint64_t& key) {
+  argmax_dpp<0xB1>(v, key);   // quad_perm [1,0,3,2]
+  argmax_dpp<0x4E>(v, key);   // quad_perm [2,3,0,1]
+  argmax_dpp<0x141>(v, key);  // row_half_mirror
+  argmax_dpp<0x140>(v, key);  // row_mirror
+  double bv = rdlane_d(v, 0);
+  uint64_t bk = rdlane_u64(key, 0);
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const double ov = __shfl_xor(v, o, 64);
-    const uint64_t ok = ((uint64_t)(uint32_t)__shfl_xor((int)(key >> 32), o, 64) << 32) |
-                        (uint32_t)__shfl_xor((int)(uint32_t)key, o, 64);
-    if (better(ov, ok, v, key)) {
-      v = ov;
-      key = ok;
+  for (int r = 1; r < 4; ++r) {
+    const double ov = rdlane_d(v, 16 * r);
+    const uint64_t ok = rdlane_u64(key, 16 * r);
+    if (better(ov, ok, bv, bk)) {
+      bv = ov;
+      bk = ok;
     }
   }
+  v = bv;
+  key = bk;
 }
 
 __device__ __forceinline__ double rdlane_d(double v, int l) {
@@ -104,6 +137,8 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
   __shared__ double sLr[R][NB + 2];      // multipliers of this workgroup's rows
   __shared__ double sL11[NB][NB + 1];    // multipliers of the panel's pivot rows
   __shared__ long sRow[NB];              // the panel's pivot rows
+  __shared__ double sPs[64];             // previous pivot row, shifted to the current column
+  __shared__ double sCand[NB];           // panel row of the published candidate
   __shared__ int sAct[R];
   __shared__ int sBad, sErr;
 
@@ -165,9 +200,10 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
       uint64_t* prev_rec = a.rec;
       bool to = false;
 
-      // Publishes the candidate record of step j from column 0 of x (and
-      // column 1 for the next-column value); the payload follows separately.
-      auto publish_header = [&](int j, const double (&lnew)[RPT], int& oq) -> uint64_t {
+      // Publishes the candidate of step j (column 0 of x; column 1 gives the
+      // next-column value): the five header words go out in one store
+      // instruction.  Returns the candidate's local row, -1 if there is none.
+      auto publish_header = [&](int j, const double (&lnew)[RPT]) -> int {
         double cv = -1.0;
         uint64_t ck = NOCAND;
 #pragma unroll
@@ -182,50 +218,53 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
           }
         }
         wave_argmax(cv, ck);
-        uint64_t* myrec = a.rec + ((long)j * G + g) * RW;
-        oq = -1;
+        int olr = -1;
+        uint64_t w2 = 0, w3 = 0, w4 = 0;
+        if (ck != NOCAND) {
+          olr = (int)((long)(ck & 0xFFFFFFFFull) - row0);
+          const int ol = olr & 63, oq = olr >> 6;
+          double h0 = x[0][0], h1 = lnew[0], h2 = x[0][1];
 #pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-          if (act[q] && ck != NOCAND && (uint64_t)row[q] == (ck & 0xFFFFFFFFull)) {
-            oq = q;
-            store_agent(myrec + 2, canon(x[q][0]));
-            store_agent(myrec + 3, canon(lnew[q]));
-            store_agent(myrec + 4, canon(x[q][1]));
-            store_agent(myrec + 1, (j == 0 && wg_bad) ? BADKEY : ck);
-            store_agent(myrec, dbits(cv));
-          }
+          for (int q = 1; q < RPT; ++q)
+            if (oq == q) {
+              h0 = x[q][0];
+              h1 = lnew[q];
+              h2 = x[q][1];
+            }
+          w2 = canon(rdlane_d(h0, ol));
+          w3 = canon(rdlane_d(h1, ol));
+          w4 = canon(rdlane_d(h2, ol));
         }
-        if (ck == NOCAND && lane == 0) {
-          store_agent(myrec + 2, 0);
-          store_agent(myrec + 3, 0);
-          store_agent(myrec + 4, 0);
-          store_agent(myrec + 1, (j == 0 && wg_bad) ? BADKEY : NOCAND);
-          store_agent(myrec, dbits(-1.0));
+        if (lane < HW) {
+          uint64_t word = dbits(cv);
+          if (lane == 1) word = (j == 0 && wg_bad) ? BADKEY : ck;
+          if (lane == 2) word = w2;
+          if (lane == 3) word = w3;
+          if (lane == 4) word = w4;
+          store_agent(a.rec + ((long)j * G + g) * RW + lane, word);
         }
-        return ck;
+        return olr;
       };
-      // Payload of the candidate published for step j (owner lane, slot oq):
-      // multipliers for the panel columns before j, current values from j on.
-      auto publish_payload = [&](int j, int oq) {
-        uint64_t* myrec = a.rec + ((long)j * G + g) * RW + HW;
-        const int jl = j - p0;
+      // Payload of the candidate published for step j (local row olr):
+      // multipliers for the panel columns before j, current values from j on,
+      // staged through LDS so that one store instruction writes it.
+      auto publish_payload = [&](int j, int olr) {
+        if (olr < 0) return;
+        const int jl = j - p0, ol = olr & 63, oq = olr >> 6;
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
-          if (q == oq) {
-            const int lr = lane + 64 * q;
-            for (int c = 0; c < jl; ++c) store_agent(myrec + c, canon(sLr[lr][c]));
+          if (q == oq && lane == ol) {
 #pragma unroll
-            for (int t = 0; t < NB; ++t)
-              if (jl + t < NB) store_agent(myrec + jl + t, canon(x[q][t]));
+            for (int t = 0; t < NB; ++t) sCand[t] = x[q][t];
           }
+        }
+        if (lane < NB) {
+          const double v = (lane < jl) ? sLr[olr][lane] : sCand[lane - jl];
+          store_agent(a.rec + ((long)j * G + g) * RW + HW + lane, canon(v));
         }
       };
 
-      {
-        int oq;
-        publish_header(p0, lprev, oq);
-        publish_payload(p0, oq);
-      }
+      publish_payload(p0, publish_header(p0, lprev));
       for (int jl = 0; jl < ns; ++jl) {
         const int j = p0 + jl;
         // ---- headers of step j ----
@@ -321,6 +360,8 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
           if (lane < jl - 1) sL11[jl - 1][lane] = raw;
           pcur = (lane >= jl && lane < NB) ? raw - lam_prev * pprev : 0.0;
         }
+        // broadcast copy: sPs[t] = pivot row j-1 in panel column jl+1+t (0 past the panel)
+        if (lane >= jl + 1) sPs[lane - jl - 1] = pcur;
         // this winner's payload: requested now, used at the next step
         uint64_t* wrec = a.rec + ((long)j * G + wg) * RW;
         pay = (lane < NB) ? load_agent(wrec + HW + lane) : 0;
@@ -334,22 +375,18 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
         }
 
         // ---- elimination: next column now, the rest after the header ----
-        const double pj1 = r1 - lam * rdlane_d(pcur, jl + 1);   // U(j, j+1)
-        const double s1 = rdlane_d(pcur, jl + 1), s2 = rdlane_d(pcur, jl + 2);
+        const double s1 = sPs[0], s2 = sPs[1];
+        const double pj1 = r1 - lam * s1;   // U(j, j+1)
         double lnew[RPT];
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
-          lnew[q] = 0.0;
           if (act[q] && row[q] == wrow) act[q] = false;
-          if (act[q]) {
-            if (pos[q] == j) pos[q] = wpos;
-            x[q][1] -= lprev[q] * s1;
-            x[q][2] -= lprev[q] * s2;
-            const double l = (pjj != 0.0) ? x[q][0] / pjj : 0.0;
-            x[q][1] -= l * pj1;
-            lnew[q] = l;
-            sLr[lane + 64 * q][jl] = l;
-          }
+          if (act[q] && pos[q] == j) pos[q] = wpos;
+          const double l = (act[q] && pjj != 0.0) ? x[q][0] / pjj : 0.0;
+          x[q][1] = (x[q][1] - lprev[q] * s1) - l * pj1;
+          x[q][2] -= lprev[q] * s2;
+          lnew[q] = l;
+          sLr[lane + 64 * q][jl] = l;
         }
         // shift: column j+1 becomes register 0
 #pragma unroll
@@ -358,21 +395,19 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
           for (int t = 0; t < NB - 1; ++t) x[q][t] = x[q][t + 1];
           x[q][NB - 1] = 0.0;
         }
-        int oq = -1;
-        if (jl + 1 < ns) publish_header(j + 1, lnew, oq);
+        const int olr = (jl + 1 < ns) ? publish_header(j + 1, lnew) : -1;
         // previous pivot's contribution to the remaining panel columns
 #pragma unroll
         for (int t = 2; t < NB - 1; ++t) {
-          const double s = rdlane_d(pcur, jl + 1 + t);
+          const double sv = sPs[t];
 #pragma unroll
-          for (int q = 0; q < RPT; ++q)
-            if (act[q]) x[q][t] -= lprev[q] * s;
+          for (int q = 0; q < RPT; ++q) x[q][t] -= lprev[q] * sv;
         }
 #pragma unroll
         for (int q = 0; q < RPT; ++q) lprev[q] = lnew[q];
         pprev = pcur;
         lam_prev = lam;
-        if (jl + 1 < ns) publish_payload(j + 1, oq);
+        publish_payload(j + 1, olr);
       }
       // the last pivot row's multipliers (row ns-1 of L11)
       if (!sErr) {
@@ -474,6 +509,11 @@ int pick_rpt(long ni) {
 }
 
 }  // namespace
+
+int lu_resident_groups(i64 ni) {
+  const int rpt = pick_rpt(ni);
+  return rpt ? (int)((ni + 64L * rpt - 1) / (64L * rpt)) : 0;
+}
 
 size_t lu_records_bytes(int d, i64 ni) {
   const int rpt = pick_rpt(ni);

@@ -303,6 +303,12 @@ __global__ __launch_bounds__(NT) void sketch_head_kernel(HeadArgs a) {
 
 static int head_pw(int d) { return d <= 320 ? 32 : (d <= 640 ? 16 : 8); }
 
+int sketch_head_groups(int d, i64 ni) {
+  const int dh = (int)std::min((i64)d, ni);
+  const int pw = head_pw(d);
+  return (dh + pw - 1) / pw;
+}
+
 size_t sketch_qr_ws_bytes(int d, i64 ni) {
   const int dh = (int)std::min((i64)d, ni);
   const int pw = head_pw(d);

@@ -71,6 +71,34 @@ _sig("qrcp_apply_qt_workspace_size", _sz, _i64, _i64, _i64)
 _sig("qrcp_apply_qt", ctypes.c_int, _vp, _i64, _i64, _i64, _vp, _vp, _i64, _i64, _i32, _vp, _sz, _vp)
 _sig("qrcp_sketch_update", ctypes.c_int, _vp, _i64, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp)
 
+
+
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_int64), ("device", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("lda", ctypes.c_int64), ("block_size", ctypes.c_int64),
+                ("sketch_factor", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("tol", ctypes.c_double), ("A", ctypes.c_void_p), ("jpiv", ctypes.c_void_p),
+                ("tau", ctypes.c_void_p), ("opts", QrcpOpts)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("rank", ctypes.c_int64), ("submit_ms", ctypes.c_double),
+                ("start_ms", ctypes.c_double), ("end_ms", ctypes.c_double)]
+
+
+_sig("qrcp_server_create", _vp, ctypes.POINTER(ServerCfg))
+_sig("qrcp_server_submit", ctypes.c_int, _vp, ctypes.POINTER(Request), ctypes.POINTER(_u64))
+_sig("qrcp_server_poll", ctypes.c_int, _vp, _u64, ctypes.POINTER(Result))
+_sig("qrcp_server_wait", ctypes.c_int, _vp, _u64, ctypes.POINTER(Result))
+_sig("qrcp_server_pending", ctypes.c_int, _vp)
+_sig("qrcp_server_destroy", None, _vp)
+
 _sig("qrcp_profile_enable", ctypes.c_int, _i32)
 _sig("qrcp_profile_num_stages", _i32)
 _sig("qrcp_profile_stage_name", ctypes.c_char_p, _i32)
@@ -83,7 +111,8 @@ EXPORTED = ["qrcp_profile_enable", "qrcp_profile_num_stages", "qrcp_profile_stag
             "qrcp_sketch", "qrcp_lu_workspace_size", "qrcp_lu_pivots",
             "qrcp_sketch_qr_workspace_size", "qrcp_sketch_qr", "qrcp_panel_workspace_size",
             "qrcp_cholqr", "qrcp_reconstruct", "qrcp_apply_qt_workspace_size", "qrcp_apply_qt",
-            "qrcp_sketch_update"]
+            "qrcp_sketch_update", "qrcp_server_create", "qrcp_server_submit", "qrcp_server_poll",
+            "qrcp_server_wait", "qrcp_server_pending", "qrcp_server_destroy"]
 
 
 class QrcpError(RuntimeError):
@@ -283,3 +312,76 @@ def profile_read() -> dict:
         out[_lib.qrcp_profile_stage_name(st).decode()] = (ms.value, int(cnt.value), fl.value)
     return out
 
+
+
+# ---------------------------------------------------------------- request server
+class Server:
+    """qrcp_server_*: concurrent factorizations of independent requests.
+
+    ``submit`` hands the library a column-major FP64 device matrix (overwritten in
+    place, as ``factor``) and returns a ticket; ``poll``/``wait`` return
+    ``(A, jpiv, tau, rank, timing)`` once the request is done, where timing holds
+    the server-clock submit/start/end times in ms.  The tensors of a request are
+    kept alive here until it is collected.
+    """
+
+    def __init__(self, slots: int = 4, hbm_budget: int = 0, device: int = 0):
+        cfg = ServerCfg(ctypes.sizeof(ServerCfg), slots, hbm_budget, device)
+        self._h = _lib.qrcp_server_create(ctypes.byref(cfg))
+        if not self._h:
+            raise QrcpError(QRCP_ERR_HIP, "qrcp_server_create")
+        self._live = {}
+
+    def submit(self, A: torch.Tensor, block_size: int, sketch_factor: float = 1.25,
+               seed: int = 42, tol: float = 0.0, *, cholqr_passes: int = 1,
+               sketch_precision: int = 0, trailing_precision: int = 0,
+               pivot_base: int = 0) -> int:
+        ptr, m, n, lda = _cm(A, "A")
+        jpiv = torch.empty(n, dtype=torch.int64, device=A.device)
+        tau = torch.empty(min(m, n), dtype=torch.float64, device=A.device)
+        # the caller's pending work on A (e.g. its initialization) must be done
+        # before a server stream reads it
+        torch.cuda.current_stream(A.device).synchronize()
+        req = Request(ctypes.sizeof(Request), m, n, lda, block_size, sketch_factor, seed, tol,
+                      ptr, jpiv.data_ptr(), tau.data_ptr(),
+                      _opts(cholqr_passes, sketch_precision, trailing_precision, pivot_base))
+        t = _u64(0)
+        _check(_lib.qrcp_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)),
+               "qrcp_server_submit")
+        self._live[t.value] = (A, jpiv, tau)
+        return t.value
+
+    def _done(self, ticket, res):
+        A, jpiv, tau = self._live.pop(ticket)
+        _check(res.status, "qrcp_server request")
+        return A, jpiv, tau, int(res.rank), {"submit_ms": res.submit_ms,
+                                             "start_ms": res.start_ms, "end_ms": res.end_ms}
+
+    def poll(self, ticket: int):
+        res = Result()
+        rc = _lib.qrcp_server_poll(self._h, ticket, ctypes.byref(res))
+        if rc == 1:
+            return None
+        if rc != 0:
+            raise KeyError(ticket)
+        return self._done(ticket, res)
+
+    def wait(self, ticket: int):
+        res = Result()
+        if _lib.qrcp_server_wait(self._h, ticket, ctypes.byref(res)) != 0:
+            raise KeyError(ticket)
+        return self._done(ticket, res)
+
+    def pending(self) -> int:
+        return int(_lib.qrcp_server_pending(self._h))
+
+    def close(self):
+        if self._h:
+            _lib.qrcp_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
