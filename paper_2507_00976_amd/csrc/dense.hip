@@ -121,8 +121,10 @@ typedef double dv4 __attribute__((ext_vector_type(4)));
 // kk x N staged as sB[t][j] (kk <= 32, M, N <= 64).  assign: C = A B, else
 // C -= A B; the C values are read before the products so that their latency
 // overlaps the matrix-core work.
+constexpr int TTP = TT + 1;  // LDS row stride of the staged operands
+
 __device__ __forceinline__ void tile_mm(double* C, long ldc, int M, int N, int kk,
-                                        const double (*sA)[TT], const double (*sB)[TT],
+                                        const double (*sA)[TTP], const double (*sB)[TTP],
                                         bool assign) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w & 1, wn = w >> 1;
@@ -175,11 +177,13 @@ __device__ __forceinline__ void tile_mm(double* C, long ldc, int M, int N, int k
 // B(t, j) read through accessors (t < kk <= 32).  upper_only skips tiles
 // strictly below the diagonal.  The operands of the next tile are loaded
 // into registers while the current tile is multiplied, so the operands must
-// not overlap the output.  blockDim.x must be 256.
-template <typename FA, typename FB>
+// not overlap the output.  AT / BT: the operand is contiguous in memory along
+// t (consecutive threads then take consecutive t, so that the loads
+// coalesce); otherwise along i / j.  blockDim.x must be 256.
+template <bool AT, bool BT, typename FA, typename FB>
 __device__ __forceinline__ void tiled_mm(double* C, long ldc, int rows, int cols, int kk,
                                          bool upper_only, bool assign, FA fa, FB fb,
-                                         double (*sA)[TT], double (*sB)[TT]) {
+                                         double (*sA)[TTP], double (*sB)[TTP]) {
   constexpr int PER = SB * TT / 256;
   const int tid = threadIdx.x;
   const int ntr = (rows + TT - 1) / TT, ntc = (cols + TT - 1) / TT, nt = ntr * ntc;
@@ -193,9 +197,11 @@ __device__ __forceinline__ void tiled_mm(double* C, long ldc, int rows, int cols
     const int M = min(TT, rows - r0), N = min(TT, cols - c0);
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int e = tid + q * 256, t = e / TT, x = e % TT;
-      ra[q] = (t < kk && x < M) ? fa(r0 + x, t) : 0.0;
-      rb[q] = (t < kk && x < N) ? fb(t, c0 + x) : 0.0;
+      const int e = tid + q * 256;
+      const int ta = AT ? e % SB : e / TT, xa = AT ? e / SB : e % TT;
+      const int tb = BT ? e % SB : e / TT, xb = BT ? e / SB : e % TT;
+      ra[q] = (ta < kk && xa < M) ? fa(r0 + xa, ta) : 0.0;
+      rb[q] = (tb < kk && xb < N) ? fb(tb, c0 + xb) : 0.0;
     }
   };
   int ti = advance(0);
@@ -204,9 +210,9 @@ __device__ __forceinline__ void tiled_mm(double* C, long ldc, int rows, int cols
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int e = tid + q * 256, t = e / TT, x = e % TT;
-      sA[t][x] = ra[q];
-      sB[t][x] = rb[q];
+      const int e = tid + q * 256;
+      sA[AT ? e % SB : e / TT][AT ? e / SB : e % TT] = ra[q];
+      sB[BT ? e % SB : e / TT][BT ? e / SB : e % TT] = rb[q];
     }
     __syncthreads();
     const int tn = advance(ti + 1);
@@ -386,8 +392,8 @@ int launch_trinv_upper(const double* R, i64 ldr, int n, double* X, i64 ldx, hipS
 __global__ __launch_bounds__(256) void potrf_upper_kernel(double* G, long ldg, int n, int* info) {
   __shared__ double sD[SB][SB + 1];
   __shared__ double sX[SB][SB + 1];
-  __shared__ double sA[SB][TT];
-  __shared__ double sB[SB][TT];
+  __shared__ double sA[SB][TTP];
+  __shared__ double sB[SB][TTP];
   __shared__ int brk;
   const int tid = threadIdx.x, lane = tid & 63;
   if (tid == 0) brk = -1;
@@ -428,11 +434,11 @@ __global__ __launch_bounds__(256) void potrf_upper_kernel(double* G, long ldg, i
     if (rest > 0) {
       // row panel R12 = R11^{-T} G12 (in place): A(i, t) = R11^{-1}(t, i)
       double* g12 = G + p0 + (long)(p0 + nb) * ldg;
-      tiled_mm(g12, ldg, nb, rest, nb, false, true,
+      tiled_mm<false, true>(g12, ldg, nb, rest, nb, false, true,
                [&](int i, int t) { return sX[t][i]; },
                [&](int t, int j) { return g12[t + (long)j * ldg]; }, sA, sB);
       // trailing update of the upper triangle: G22 -= R12^T R12
-      tiled_mm(G + (p0 + nb) + (long)(p0 + nb) * ldg, ldg, rest, rest, nb, true, false,
+      tiled_mm<true, true>(G + (p0 + nb) + (long)(p0 + nb) * ldg, ldg, rest, rest, nb, true, false,
                [&](int i, int t) { return g12[t + (long)i * ldg]; },
                [&](int t, int j) { return g12[t + (long)j * ldg]; }, sA, sB);
     }
@@ -459,8 +465,8 @@ __global__ __launch_bounds__(256) void headlu_kernel(double* Q, long ldq, int k,
   __shared__ double sD[SB][SB + 1];
   __shared__ double sXu[SB][SB + 1];
   __shared__ double sXl[SB][SB + 1];
-  __shared__ double sA[SB][TT];
-  __shared__ double sB[SB][TT];
+  __shared__ double sA[SB][TTP];
+  __shared__ double sB[SB][TTP];
   const int tid = threadIdx.x, lane = tid & 63;
   for (int p0 = 0; p0 < k; p0 += SB) {
     const int nb = min(SB, k - p0), rest = k - p0 - nb;
@@ -502,15 +508,15 @@ __global__ __launch_bounds__(256) void headlu_kernel(double* Q, long ldq, int k,
       double* a21 = Q + (p0 + nb) + (long)p0 * ldq;   // rows below the block
       double* a12 = Q + p0 + (long)(p0 + nb) * ldq;   // columns right of the block
       // L21 = A21 U11^{-1}
-      tiled_mm(a21, ldq, rest, nb, nb, false, true,
+      tiled_mm<false, false>(a21, ldq, rest, nb, nb, false, true,
                [&](int i, int t) { return a21[i + (long)t * ldq]; },
                [&](int t, int j) { return sXu[t][j]; }, sA, sB);
       // U12 = L11^{-1} A12
-      tiled_mm(a12, ldq, nb, rest, nb, false, true,
+      tiled_mm<false, true>(a12, ldq, nb, rest, nb, false, true,
                [&](int i, int t) { return sXl[i][t]; },
                [&](int t, int j) { return a12[t + (long)j * ldq]; }, sA, sB);
       // A22 -= L21 U12
-      tiled_mm(Q + (p0 + nb) + (long)(p0 + nb) * ldq, ldq, rest, rest, nb, false, false,
+      tiled_mm<false, true>(Q + (p0 + nb) + (long)(p0 + nb) * ldq, ldq, rest, rest, nb, false, false,
                [&](int i, int t) { return a21[i + (long)t * ldq]; },
                [&](int t, int j) { return a12[t + (long)j * ldq]; }, sA, sB);
     }

@@ -69,10 +69,9 @@ __device__ __forceinline__ T cvt(double x) {
   return (T)x;
 }
 
-template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, typename T>
+template <int BM, int BN, int WGM, int WGN, int BK, bool TA, bool TB, typename T>
 __device__ __forceinline__ void gemm_body(const GemmArgs& g) {
   constexpr int NTH = 64 * WGM * WGN;
-  constexpr int BK = 16;
   constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int FM = WM / 16, FN = WN / 16;
   constexpr int LA = BM * BK / NTH, LB = BN * BK / NTH;
@@ -210,9 +209,9 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g) {
 // Named instances: the trailing update's two big products and the sketch get
 // their own kernel symbols so that profiles attribute time to them.
 #define QRCP_GEMM_KERNEL(NAME)                                                              \
-  template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, typename T>                   \
+  template <int BM, int BN, int WGM, int WGN, int BK, bool TA, bool TB, typename T>           \
   __global__ __launch_bounds__(64 * WGM * WGN) void NAME(GemmArgs g) {                        \
-    gemm_body<BM, BN, WGM, WGN, TA, TB, T>(g);                                                \
+    gemm_body<BM, BN, WGM, WGN, BK, TA, TB, T>(g);                                            \
   }
 QRCP_GEMM_KERNEL(gemm_kernel)
 QRCP_GEMM_KERNEL(trailing_update_kernel)
@@ -321,28 +320,29 @@ __global__ void scale_kernel(double* C, long ldc, int M, int N, double beta) {
   *c = (beta == 0.0) ? 0.0 : beta * (*c);
 }
 
-template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, typename T>
+template <int BM, int BN, int WGM, int WGN, int BK, bool TA, bool TB, typename T>
 static void launch_tile(const GemmArgs& g, int splits, hipStream_t st) {
   dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, splits);
   dim3 block(64 * WGM * WGN);
   switch (g.kind) {
     case GemmKind::TrailingUpdate:
-      hipLaunchKernelGGL((trailing_update_kernel<BM, BN, WGM, WGN, TA, TB, T>), grid, block, 0, st, g);
+      hipLaunchKernelGGL((trailing_update_kernel<BM, BN, WGM, WGN, BK, TA, TB, T>), grid, block, 0, st, g);
       break;
     case GemmKind::TrailingW:
-      hipLaunchKernelGGL((trailing_w_kernel<BM, BN, WGM, WGN, TA, TB, T>), grid, block, 0, st, g);
+      hipLaunchKernelGGL((trailing_w_kernel<BM, BN, WGM, WGN, BK, TA, TB, T>), grid, block, 0, st, g);
       break;
     case GemmKind::Sketch:
-      hipLaunchKernelGGL((sketch_gemm_kernel<BM, BN, WGM, WGN, TA, TB, T>), grid, block, 0, st, g);
+      hipLaunchKernelGGL((sketch_gemm_kernel<BM, BN, WGM, WGN, BK, TA, TB, T>), grid, block, 0, st, g);
       break;
     default:
-      hipLaunchKernelGGL((gemm_kernel<BM, BN, WGM, WGN, TA, TB, T>), grid, block, 0, st, g);
+      hipLaunchKernelGGL((gemm_kernel<BM, BN, WGM, WGN, BK, TA, TB, T>), grid, block, 0, st, g);
   }
 }
 
 // Tile configuration: 0 = automatic; 1 = 64x64 (4 waves); 2 = 128x128 (4 waves);
-// 3 = 128x128 (8 waves); 4 = 128x64 (4 waves).  QRCP_GEMM_TILE overrides the
-// automatic choice (used for tuning sweeps).
+// 3 = 128x128 (8 waves); 4 = 128x64 (4 waves); 5 = 128x128 (8 waves, k chunk
+// 32); 6 = 256x128 (8 waves); 7 = 128x256 (8 waves).  QRCP_GEMM_TILE overrides
+// the automatic choice (used for tuning sweeps).
 static int tile_override() {
   static int v = -1;
   if (v < 0) {
@@ -360,10 +360,13 @@ static void launch_shape(const GemmArgs& g, int splits, hipStream_t st) {
     cfg = (g.M >= 128 && g.N >= 128 && tiles128 >= 240) ? 3 : 1;
   }
   switch (cfg) {
-    case 2: launch_tile<128, 128, 2, 2, TA, TB, T>(g, splits, st); break;
-    case 3: launch_tile<128, 128, 2, 4, TA, TB, T>(g, splits, st); break;
-    case 4: launch_tile<128, 64, 2, 2, TA, TB, T>(g, splits, st); break;
-    default: launch_tile<64, 64, 2, 2, TA, TB, T>(g, splits, st); break;
+    case 2: launch_tile<128, 128, 2, 2, 16, TA, TB, T>(g, splits, st); break;
+    case 3: launch_tile<128, 128, 2, 4, 16, TA, TB, T>(g, splits, st); break;
+    case 4: launch_tile<128, 64, 2, 2, 16, TA, TB, T>(g, splits, st); break;
+    case 5: launch_tile<128, 128, 2, 4, 32, TA, TB, T>(g, splits, st); break;
+    case 6: launch_tile<256, 128, 2, 4, 16, TA, TB, T>(g, splits, st); break;
+    case 7: launch_tile<128, 256, 2, 4, 16, TA, TB, T>(g, splits, st); break;
+    default: launch_tile<64, 64, 2, 2, 16, TA, TB, T>(g, splits, st); break;
   }
 }
 
@@ -394,7 +397,7 @@ int gemm(bool ta, bool tb, Prec prec, GemmArgs g, double* split_ws, size_t split
   int splits = 1;
   if (split_ws && !g.bcol) splits = gemm_pick_splits(g.M, g.N, g.K);
   if (splits > 1 && gemm_splitk_bytes(g.M, g.N, splits) > split_ws_bytes) splits = 1;
-  const long BKc = (prec == Prec::BF16) ? 32 : 16;
+  const long BKc = 32;
   long chunk = (g.K + splits - 1) / splits;
   chunk = (chunk + BKc - 1) / BKc * BKc;
   splits = (int)((g.K + chunk - 1) / chunk);

@@ -76,44 +76,36 @@ __device__ __forceinline__ uint64_t rdlane_u64(uint64_t v, int l) {
   return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
 }
 
-// One exchange step of the argmax inside rows of 16 lanes: DPP moves (no LDS).
 template <int CTRL>
-__device__ __forceinline__ void argmax_dpp(double& v, uint64_t& key) {
-  const long long vb = __double_as_longlong(v);
-  const int vlo = __builtin_amdgcn_update_dpp((int)vb, (int)vb, CTRL, 0xF, 0xF, false);
-  const int vhi = __builtin_amdgcn_update_dpp((int)(vb >> 32), (int)(vb >> 32), CTRL, 0xF, 0xF, false);
-  const int klo = __builtin_amdgcn_update_dpp((int)key, (int)key, CTRL, 0xF, 0xF, false);
-  const int khi = __builtin_amdgcn_update_dpp((int)(key >> 32), (int)(key >> 32), CTRL, 0xF, 0xF, false);
-  const double ov = __longlong_as_double(((long long)vhi << 32) | (uint32_t)vlo);
-  const uint64_t ok = ((uint64_t)(uint32_t)khi << 32) | (uint32_t)klo;
-  if (better(ov, ok, v, key)) {
-    v = ov;
-    key = ok;
-  }
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (uint32_t)lo);
 }
 
-// Wave-wide argmax of (v, key); every lane gets the result.  Lanes exchange
-// with lane^1, lane^2 (quad permutations), then the mirrored lane of the half
-// row and of the row, so every lane of a 16-lane row holds the row's best;
-// the four rows are combined through scalar reads.
+// Wave-wide argmax of (v, key), v never NaN; every lane gets the result.  The
+// maximum value is reduced with DPP moves inside rows of 16 lanes (lane^1,
+// lane^2, mirrored lane of the half row, of the row) and scalar reads of the
+// four rows; the key is the smallest among the lanes that hold the maximum
+// (one lane in the common case).
 __device__ __forceinline__ void wave_argmax(double& v, uint64_t& key) {
-  argmax_dpp<0xB1>(v, key);   // quad_perm [1,0,3,2]
-  argmax_dpp<0x4E>(v, key);   // quad_perm [2,3,0,1]
-  argmax_dpp<0x141>(v, key);  // row_half_mirror
-  argmax_dpp<0x140>(v, key);  // row_mirror
-  double bv = rdlane_d(v, 0);
-  uint64_t bk = rdlane_u64(key, 0);
-#pragma unroll
-  for (int r = 1; r < 4; ++r) {
-    const double ov = rdlane_d(v, 16 * r);
-    const uint64_t ok = rdlane_u64(key, 16 * r);
-    if (better(ov, ok, bv, bk)) {
-      bv = ov;
-      bk = ok;
-    }
+  double m = v;
+  m = fmax(m, dpp_d<0xB1>(m));   // quad_perm [1,0,3,2]
+  m = fmax(m, dpp_d<0x4E>(m));   // quad_perm [2,3,0,1]
+  m = fmax(m, dpp_d<0x141>(m));  // row_half_mirror
+  m = fmax(m, dpp_d<0x140>(m));  // row_mirror
+  const double mx = fmax(fmax(rdlane_d(m, 0), rdlane_d(m, 16)), fmax(rdlane_d(m, 32), rdlane_d(m, 48)));
+  uint64_t tie = __ballot(v == mx);
+  uint64_t best = ~0ull;
+  while (tie) {
+    const int l = __ffsll((unsigned long long)tie) - 1;
+    tie &= tie - 1;
+    const uint64_t k = rdlane_u64(key, l);
+    if (k < best) best = k;
   }
-  v = bv;
-  key = bk;
+  v = mx;
+  key = best;
 }
 
 __device__ __forceinline__ double rdlane_d(double v, int l) {

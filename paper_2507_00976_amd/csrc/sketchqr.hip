@@ -14,6 +14,7 @@
 // kernels.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "wave32.hpp"
 
 namespace qrcp {
 
@@ -299,6 +300,261 @@ __global__ __launch_bounds__(NT) void sketch_head_kernel(HeadArgs a) {
   if (tid == 0) store_agent_i32(a.flags + w, 1);
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident variant for d <= 8 * NR (NR <= 40): thread (rg, cg) of the
+// 256 holds rows rg, rg + 8, ... of panel column cg in registers.  One
+// Householder column costs one workgroup barrier: column j is broadcast inside
+// each wave through LDS, one fused reduction gives, for every panel column c,
+// x_j . x_c over the rows below the diagonal: for c > j the reflector's action
+// on column c, for c = j the squared norm, for c < j the Gram entry v_c^T v_j
+// that yields the panel's T by the UT transform once the panel is done.
+// Every thread then updates its own column.  Previous panels are applied
+// as (I - V_q T_q V_q^T)^T with V_q staged whole in LDS.
+// ---------------------------------------------------------------------------
+constexpr int RG = 8;    // row groups
+constexpr int PWR = 32;  // panel width
+constexpr int LDP = 33;  // padded LDS row stride
+
+template <int NR>
+__global__ __launch_bounds__(NT) void sketch_head_reg_kernel(HeadArgs a) {
+  extern __shared__ double smem[];
+  const int d = a.d, dh = a.dh;
+  double* sV = smem;                       // d x LDP: V_q of the panel being applied
+  double* sP = sV + (size_t)d * LDP;       // 4 x PWR x LDP: per-wave partial products
+  double* sW = sP + 4 * PWR * LDP;         // PWR x LDP: W = V_q^T C, then T_q^T W
+  double* sT = sW + PWR * LDP;             // PWR x LDP: T of the panel (own or applied)
+  double* sXb = sT + PWR * LDP;            // d: broadcast column
+  double* sRed = sXb + d;                  // 2 x 4 x PWR: per-wave reduced sums
+  double* sRowJ = sRed + 2 * 4 * PWR;      // 2 x PWR: row rj of the panel
+  double* sG = sRowJ + 2 * PWR;            // PWR x LDP: G(i, j) = v_i^T v_j, i < j
+  double* sTau = sG + PWR * LDP;           // PWR
+  double* sInv = sTau + PWR;               // PWR: alpha_j - beta_j (1 when tau_j = 0)
+  __shared__ int sbad;
+
+  const int w = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rg = tid >> 5, cg = tid & 31;
+  const int c0 = w * PWR;
+  const int ncol = min(PWR, dh - c0);
+  const bool colok = cg < ncol;
+
+  double x[NR];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    const int r = rg + RG * i;
+    x[i] = (colok && r < d) ? a.B[r + (long)(c0 + cg) * a.ldb] : 0.0;
+  }
+  if (tid == 0) sbad = 0;
+
+  // ---- apply the reflectors of the panels before mine ----
+  for (int p = 0; p < w; ++p) {
+    const int p0 = p * PWR;
+    const int pc = min(PWR, dh - p0);
+    if (tid == 0) {
+      long spins = 0;
+      while (load_agent_i32(a.flags + p) == 0) {
+        if (++spins > kSpinLimit) { sbad = 1; break; }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __syncthreads();
+    if (sbad) {
+      if (tid == 0) store_agent_i32(a.status, QRCP_ERR_TIMEOUT);
+      return;
+    }
+    __threadfence();
+    // stage V_q (rows p0 .. d) and T_q
+    for (int e = tid; e < (d - p0) * PWR; e += NT) {
+      const int rr = p0 + e / PWR, aa = e % PWR;
+      sV[rr * LDP + aa] = (aa < pc) ? a.V[rr + (long)(p0 + aa) * d] : 0.0;
+    }
+    for (int e = tid; e < PWR * PWR; e += NT)
+      sT[(e % PWR) * LDP + e / PWR] = a.T[(long)p * PWR * PWR + e];  // T(i, j) at e = i + PWR j
+    __syncthreads();
+    // partial W(aa, cg) over my rows
+    double pw[PWR];
+#pragma unroll
+    for (int aa = 0; aa < PWR; ++aa) pw[aa] = 0.0;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int r = rg + RG * i;
+      if (r >= p0 && r < d) {
+#pragma unroll
+        for (int aa = 0; aa < PWR; ++aa) pw[aa] += sV[r * LDP + aa] * x[i];
+      }
+    }
+#pragma unroll
+    for (int aa = 0; aa < PWR; ++aa) pw[aa] += __shfl_xor(pw[aa], 32, 64);
+    if (lane < 32) {
+#pragma unroll
+      for (int aa = 0; aa < PWR; ++aa) sP[(wave * PWR + aa) * LDP + cg] = pw[aa];
+    }
+    __syncthreads();
+    // W(aa, cg) for aa = 4 rg .. 4 rg + 3
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int aa = 4 * rg + q;
+      double t = 0.0;
+#pragma unroll
+      for (int ww = 0; ww < 4; ++ww) t += sP[(ww * PWR + aa) * LDP + cg];
+      sW[aa * LDP + cg] = t;
+    }
+    __syncthreads();
+    // W'(aa, cg) = sum_{t <= aa} T(t, aa) W(t, cg)
+    double w2[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int aa = 4 * rg + q;
+      double t = 0.0;
+      for (int tt = 0; tt <= aa; ++tt) t += sT[tt * LDP + aa] * sW[tt * LDP + cg];
+      w2[q] = t;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sW[(4 * rg + q) * LDP + cg] = w2[q];
+    __syncthreads();
+    double wv[PWR];
+#pragma unroll
+    for (int aa = 0; aa < PWR; ++aa) wv[aa] = sW[aa * LDP + cg];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int r = rg + RG * i;
+      if (r >= p0 && r < d) {
+        double t = 0.0;
+#pragma unroll
+        for (int aa = 0; aa < PWR; ++aa) t += sV[r * LDP + aa] * wv[aa];
+        x[i] -= t;
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- factor my panel ----
+  // Columns stay unscaled while the panel is factored (x_j below row rj; the
+  // reflector is v_j = x_j / (alpha_j - beta_j)); the Gram entries
+  // G(i, j) = v_i^T v_j come out of the same fused reduction and give T at
+  // the end by the UT transform T^{-1} = diag(1/tau) + striu(G).
+  for (int j = 0; j < ncol; ++j) {
+    const int rj = c0 + j;
+    const int buf = j & 1;
+    // broadcast column j inside each wave (writer and readers share the wave)
+    if (cg == j) {
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        const int r = rg + RG * i;
+        if (r < d) sXb[r] = x[i];
+      }
+    }
+    double xj[NR];
+    double sacc = 0.0;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int r = rg + RG * i;
+      xj[i] = (r > rj && r < d) ? sXb[r] : 0.0;
+      sacc += xj[i] * x[i];
+    }
+    sacc += __shfl_xor(sacc, 32, 64);
+    if (lane < 32) sRed[(buf * 4 + wave) * PWR + cg] = sacc;
+    if (rg == (rj & 7)) {
+#pragma unroll
+      for (int i = 0; i < NR; ++i)
+        if (i == (rj >> 3)) sRowJ[buf * PWR + cg] = x[i];
+    }
+    __syncthreads();
+    double S = 0.0, xx = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < 4; ++ww) {
+      S += sRed[(buf * 4 + ww) * PWR + cg];
+      xx += sRed[(buf * 4 + ww) * PWR + j];
+    }
+    const double alpha = sRowJ[buf * PWR + j];
+    double beta = alpha, tau = 0.0, inv = 1.0;
+    if (xx != 0.0) {
+      const double nrm = sqrt(alpha * alpha + xx);
+      beta = (alpha < 0.0) ? nrm : -nrm;
+      tau = (beta - alpha) / beta;
+      inv = alpha - beta;
+    }
+    if (colok && cg > j) {
+      if (tau != 0.0) {
+        const double wc = sRowJ[buf * PWR + cg] + S / inv;
+        const double f = tau * wc;
+        const double fv = f / inv;
+#pragma unroll
+        for (int i = 0; i < NR; ++i) x[i] -= fv * xj[i];   // xj is 0 at and above row rj
+        if (rg == (rj & 7)) {
+#pragma unroll
+          for (int i = 0; i < NR; ++i)
+            if (i == (rj >> 3)) x[i] -= f;
+        }
+      }
+    } else if (cg == j && rg == (rj & 7)) {
+#pragma unroll
+      for (int i = 0; i < NR; ++i)
+        if (i == (rj >> 3)) x[i] = beta;
+    }
+    // G(i, j) = v_i^T v_j = (x_i(rj) + S_i / inv_j) / inv_i for i < j
+    if (tid < PWR) {
+      const int i = tid;
+      if (i < j) sG[i * LDP + j] = (sRowJ[buf * PWR + i] + S / inv) / sInv[i];
+      if (i == 0) {
+        sTau[j] = tau;
+        sInv[j] = inv;
+        a.tau[rj] = tau;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- T of the panel: invert diag(1/tau) + striu(G) (a zero tau decouples
+  // its index: its row and column of T are zero) ----
+  if (tid < 64) {
+    double tx[W32], ty[W32];
+#pragma unroll
+    for (int r = 0; r < W32; ++r) {
+      double v = 0.0;
+      if (lane < ncol && r < ncol) {
+        const double tr = sTau[r], tc = sTau[lane];
+        if (tr == 0.0 || tc == 0.0) v = (r == lane) ? 1.0 : 0.0;
+        else if (r == lane) v = 1.0 / tc;
+        else if (r < lane) v = sG[r * LDP + lane];
+      }
+      tx[r] = v;
+    }
+    wave_inv_upper32_col(tx, ty, ncol);
+    if (lane < PWR) {
+#pragma unroll
+      for (int r = 0; r < W32; ++r) {
+        double v = (lane < ncol && r < ncol) ? ty[r] : 0.0;
+        if (lane < ncol && r == lane && sTau[lane] == 0.0) v = 0.0;
+        sT[r * LDP + lane] = v;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- publish V (clean, scaled), R, T ----
+  if (colok) {
+    const int rc = c0 + cg;
+    const double iv = sInv[cg];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int r = rg + RG * i;
+      if (r < d) {
+        a.V[r + (long)rc * d] = (r < rc) ? 0.0 : (r == rc ? 1.0 : x[i] / iv);
+        a.R[r + (long)rc * a.ldr] = (r <= rc) ? x[i] : 0.0;
+      }
+    }
+  }
+  for (int e = tid; e < PWR * PWR; e += NT) {
+    const int i = e % PWR, jj = e / PWR;
+    a.T[(long)w * PWR * PWR + e] = (i < ncol && jj < ncol) ? sT[i * LDP + jj] : 0.0;
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) store_agent_i32(a.flags + w, 1);
+}
+
 }  // namespace
 
 static int head_pw(int d) { return d <= 320 ? 32 : (d <= 640 ? 16 : 8); }
@@ -350,12 +606,22 @@ int run_sketch_qr(const double* B, int d, i64 ni, i64 ldb, double* R, i64 ldr, v
   QRCP_TRY(launch_fill_u64((uint64_t*)flags, (np + 1) / 2, 0ull, st));
   HeadArgs args{B, (long)ldb, d, dh, pw, R, (long)ldr, V, tau, Tp, flags, status_dev};
   void* params[] = {&args};
+  if (d <= 320) {
+    const size_t smem_r = ((size_t)d * LDP + 4 * PWR * LDP + 2 * PWR * LDP + d + 8 * PWR + 2 * PWR +
+                           PWR * LDP + 2 * PWR) * 8;
+    const void* fr = d <= 80 ? (const void*)sketch_head_reg_kernel<10>
+                   : d <= 160 ? (const void*)sketch_head_reg_kernel<20>
+                              : (const void*)sketch_head_reg_kernel<40>;
+    QRCP_HIP(hipFuncSetAttribute(fr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_r));
+    QRCP_TRY(launch_resident(fr, dim3(np), dim3(NT), params, smem_r, st));
+  } else {
   const size_t smem = ((size_t)pw * (d + 1) + VLD * pw + 2 * pw * pw + std::max<size_t>((size_t)pw * pw, NT)) * 8;
   const void* fn = pw == 32 ? (const void*)sketch_head_kernel<32>
                  : pw == 16 ? (const void*)sketch_head_kernel<16>
                             : (const void*)sketch_head_kernel<8>;
   QRCP_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
   QRCP_TRY(launch_resident(fn, dim3(np), dim3(NT), params, smem, st));
+  }
 
   if (ni > dh) {
     // T = (diag(1/tau) + striu(V^T V))^{-1}
