@@ -66,6 +66,16 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
+// Ordering point for data one lane of a wave writes to LDS and other lanes of
+// the same wave read afterwards: a wave's LDS operations execute in order, and
+// this keeps the compiler from moving the accesses across it (without it a
+// load may be hoisted above the store, the writing lane's value forwarded).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Bit-level access for the cross-workgroup record exchange.
 __device__ __forceinline__ uint64_t dbits(double x) { return __double_as_longlong(x); }
 __device__ __forceinline__ double bitsd(uint64_t x) { return __longlong_as_double((long long)x); }

@@ -235,14 +235,17 @@ __device__ __forceinline__ void tiled_mm(double* C, long ldc, int rows, int cols
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void trinv_diag_kernel(const double* R, long ldr, int n,
                                                          double* X, long ldx) {
+  __shared__ double sR[W32][W32 + 1];
   const int tid = threadIdx.x, lane = tid & 63;
   const int p0 = blockIdx.x * W32, nb = min(W32, n - p0);
+  for (int e = tid; e < W32 * W32; e += blockDim.x) {
+    const int r = e % W32, c = e / W32;
+    sR[r][c] = (r < nb && c < nb && r <= c) ? R[(p0 + r) + (long)(p0 + c) * ldr] : 0.0;
+  }
+  __syncthreads();
   if (tid < 64) {
-    double x[W32], y[W32];
-#pragma unroll
-    for (int r = 0; r < W32; ++r)
-      x[r] = (lane < nb && r <= lane) ? R[(p0 + r) + (long)(p0 + lane) * ldr] : 0.0;
-    wave_inv_upper32_col(x, y, nb);
+    double y[W32];
+    wave_inv_upper32(&sR[0][0], W32 + 1, y, nb);
     if (lane < nb) {
 #pragma unroll
       for (int r = 0; r < W32; ++r)
@@ -394,6 +397,7 @@ __global__ __launch_bounds__(256) void potrf_upper_kernel(double* G, long ldg, i
   __shared__ double sX[SB][SB + 1];
   __shared__ double sA[SB][TTP];
   __shared__ double sB[SB][TTP];
+  __shared__ double sBc[64];
   __shared__ int brk;
   const int tid = threadIdx.x, lane = tid & 63;
   if (tid == 0) brk = -1;
@@ -409,16 +413,16 @@ __global__ __launch_bounds__(256) void potrf_upper_kernel(double* G, long ldg, i
       double x[W32];
 #pragma unroll
       for (int r = 0; r < W32; ++r) x[r] = (lane < SB) ? sD[r][lane] : 0.0;
-      const int t = wave_potrf32_col(x, nb);
+      const int t = wave_potrf32_col(x, nb, sBc);
       if (lane < SB) {
 #pragma unroll
-        for (int r = 0; r < W32; ++r) sD[r][lane] = x[r];
+        for (int r = 0; r < W32; ++r) sD[r][lane] = (r <= lane) ? x[r] : 0.0;
       }
       if (t < nb) {
         if (lane == 0) brk = p0 + t;
       } else if (rest > 0) {
         double y[W32];
-        wave_inv_upper32_col(x, y, nb);
+        wave_inv_upper32(&sD[0][0], SB + 1, y, nb);
         if (lane < SB) {
 #pragma unroll
           for (int r = 0; r < W32; ++r) sX[r][lane] = y[r];
@@ -467,6 +471,7 @@ __global__ __launch_bounds__(256) void headlu_kernel(double* Q, long ldq, int k,
   __shared__ double sXl[SB][SB + 1];
   __shared__ double sA[SB][TTP];
   __shared__ double sB[SB][TTP];
+  __shared__ double sBc[64];
   const int tid = threadIdx.x, lane = tid & 63;
   for (int p0 = 0; p0 < k; p0 += SB) {
     const int nb = min(SB, k - p0), rest = k - p0 - nb;
@@ -480,19 +485,19 @@ __global__ __launch_bounds__(256) void headlu_kernel(double* Q, long ldq, int k,
       double x[W32];
 #pragma unroll
       for (int c = 0; c < W32; ++c) x[c] = (lane < SB) ? sD[lane][c] : 0.0;
-      wave_lu32_signmod_row(x, nb, dsig + p0);
+      wave_lu32_signmod_row(x, nb, dsig + p0, sBc);
       if (lane < SB) {
 #pragma unroll
         for (int c = 0; c < W32; ++c) sD[lane][c] = x[c];
       }
       if (rest > 0) {
         double y[W32];
-        wave_inv_upper32_row(x, y, nb);
+        wave_inv_upper32(&sD[0][0], SB + 1, y, nb);
         if (lane < SB) {
 #pragma unroll
           for (int r = 0; r < W32; ++r) sXu[r][lane] = y[r];
         }
-        wave_inv_unit_lower32_row(x, y, nb);
+        wave_inv_unit_lower32(&sD[0][0], SB + 1, y, nb);
         if (lane < SB) {
 #pragma unroll
           for (int r = 0; r < W32; ++r) sXl[r][lane] = y[r];

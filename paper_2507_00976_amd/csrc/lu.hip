@@ -250,6 +250,7 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
             for (int t = 0; t < NB; ++t) sCand[t] = x[q][t];
           }
         }
+        wave_lds_sync();
         if (lane < NB) {
           const double v = (lane < jl) ? sLr[olr][lane] : sCand[lane - jl];
           store_agent(a.rec + ((long)j * G + g) * RW + HW + lane, canon(v));
@@ -354,6 +355,7 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
         }
         // broadcast copy: sPs[t] = pivot row j-1 in panel column jl+1+t (0 past the panel)
         if (lane >= jl + 1) sPs[lane - jl - 1] = pcur;
+        wave_lds_sync();
         // this winner's payload: requested now, used at the next step
         uint64_t* wrec = a.rec + ((long)j * G + wg) * RW;
         pay = (lane < NB) ? load_agent(wrec + HW + lane) : 0;
@@ -400,6 +402,7 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
         pprev = pcur;
         lam_prev = lam;
         publish_payload(j + 1, olr);
+        wave_lds_sync();  // this step's LDS reads before the next step's writes
       }
       // the last pivot row's multipliers (row ns-1 of L11)
       if (!sErr) {

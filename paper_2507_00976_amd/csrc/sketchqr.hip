@@ -40,6 +40,7 @@ struct HeadArgs {
 };
 
 typedef double hv4 __attribute__((ext_vector_type(4)));
+typedef double dv4 __attribute__((ext_vector_type(4)));
 
 // W(32 x 32) = V_p^T C over rows [p0, d): V_p staged from global in row chunks,
 // C in LDS.  Wave w owns the 16 x 16 block (w & 1, w >> 1) of W; FP64 MFMA.
@@ -301,48 +302,53 @@ __global__ __launch_bounds__(NT) void sketch_head_kernel(HeadArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Register-resident variant for d <= 8 * NR (NR <= 40): thread (rg, cg) of the
-// 256 holds rows rg, rg + 8, ... of panel column cg in registers.  One
-// Householder column costs one workgroup barrier: column j is broadcast inside
-// each wave through LDS, one fused reduction gives, for every panel column c,
-// x_j . x_c over the rows below the diagonal: for c > j the reflector's action
-// on column c, for c = j the squared norm, for c < j the Gram entry v_c^T v_j
-// that yields the panel's T by the UT transform once the panel is done.
-// Every thread then updates its own column.  Previous panels are applied
-// as (I - V_q T_q V_q^T)^T with V_q staged whole in LDS.
+// Register-resident variant for d <= 320.  Wave s (0..3), lane j + 16 kk of
+// the 256 threads holds panel columns j and 16 + j in rows 16 i + 4 s + kk
+// (i < NR2, rows past d are zero).  In this layout a lane's register is the
+// matrix-core operand B(k = kk, j) of a 4-row slab, so applying a previous
+// panel, C -= V_q (T_q^T (V_q^T C)), runs on the FP64 matrix cores straight
+// from registers (V_q staged in LDS).  One Householder column costs one
+// workgroup barrier: the column is broadcast inside each wave through LDS
+// (the rows a wave needs are the rows it holds), one fused reduction gives,
+// for every panel column c, x_j . x_c over the rows below the diagonal (the
+// reflector's action for c > j, the squared norm for c = j, the Gram entry
+// v_c^T v_j for c < j, from which the panel's T follows by the UT transform).
 // ---------------------------------------------------------------------------
-constexpr int RG = 8;    // row groups
 constexpr int PWR = 32;  // panel width
 constexpr int LDP = 33;  // padded LDS row stride
 
-template <int NR>
+template <int NR2>
 __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(HeadArgs a) {
+  static_assert(NR2 % 4 == 0, "row slabs come in groups of four");
   extern __shared__ double smem[];
+  constexpr int DP = 16 * NR2;             // rows held (>= d); rows d.. are zero
   const int d = a.d, dh = a.dh;
-  double* sV = smem;                       // d x LDP: V_q of the panel being applied
-  double* sP = sV + (size_t)d * LDP;       // 4 x PWR x LDP: per-wave partial products
-  double* sW = sP + 4 * PWR * LDP;         // PWR x LDP: W = V_q^T C, then T_q^T W
-  double* sT = sW + PWR * LDP;             // PWR x LDP: T of the panel (own or applied)
-  double* sXb = sT + PWR * LDP;            // d: broadcast column
-  double* sRed = sXb + d;                  // 2 x 4 x PWR: per-wave reduced sums
+  double* sV = smem;                       // DP x LDP: V_q of the panel being applied
+  double* sWp = sV + (size_t)DP * LDP;     // 4 x PWR x LDP: per-wave partial V_q^T C
+  double* sW = sWp + 4 * PWR * LDP;        // PWR x LDP: W = V_q^T C
+  double* sW2 = sW + PWR * LDP;            // PWR x LDP: T_q^T W (then the Gram entries G)
+  double* sG = sW2;
+  double* sT = sW2 + PWR * LDP;            // PWR x LDP: T (applied panel's, then own)
+  double* sXb = sT + PWR * LDP;            // DP: broadcast column
+  double* sRed = sXb + DP;                 // 2 x 4 x PWR: per-wave column sums
   double* sRowJ = sRed + 2 * 4 * PWR;      // 2 x PWR: row rj of the panel
-  double* sG = sRowJ + 2 * PWR;            // PWR x LDP: G(i, j) = v_i^T v_j, i < j
-  double* sTau = sG + PWR * LDP;           // PWR
+  double* sTau = sRowJ + 2 * PWR;          // PWR
   double* sInv = sTau + PWR;               // PWR: alpha_j - beta_j (1 when tau_j = 0)
   __shared__ int sbad;
 
   const int w = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int rg = tid >> 5, cg = tid & 31;
+  const int tid = threadIdx.x, lane = tid & 63, ws = tid >> 6;
+  const int j = lane & 15, kk = lane >> 4;
   const int c0 = w * PWR;
   const int ncol = min(PWR, dh - c0);
-  const bool colok = cg < ncol;
+  const int rbase = 4 * ws + kk;           // my rows: rbase + 16 i
 
-  double x[NR];
+  double x0[NR2], x1[NR2];                 // columns j and 16 + j
 #pragma unroll
-  for (int i = 0; i < NR; ++i) {
-    const int r = rg + RG * i;
-    x[i] = (colok && r < d) ? a.B[r + (long)(c0 + cg) * a.ldb] : 0.0;
+  for (int i = 0; i < NR2; ++i) {
+    const int r = rbase + 16 * i;
+    x0[i] = (j < ncol && r < d) ? a.B[r + (long)(c0 + j) * a.ldb] : 0.0;
+    x1[i] = (16 + j < ncol && r < d) ? a.B[r + (long)(c0 + 16 + j) * a.ldb] : 0.0;
   }
   if (tid == 0) sbad = 0;
 
@@ -363,67 +369,71 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(HeadArgs a) {
       return;
     }
     __threadfence();
-    // stage V_q (rows p0 .. d) and T_q
-    for (int e = tid; e < (d - p0) * PWR; e += NT) {
-      const int rr = p0 + e / PWR, aa = e % PWR;
-      sV[rr * LDP + aa] = (aa < pc) ? a.V[rr + (long)(p0 + aa) * d] : 0.0;
+    for (int e = tid; e < DP * PWR; e += NT) {
+      const int rr = e / PWR, aa = e % PWR;
+      sV[rr * LDP + aa] = (aa < pc && rr >= p0 && rr < d) ? a.V[rr + (long)(p0 + aa) * d] : 0.0;
     }
     for (int e = tid; e < PWR * PWR; e += NT)
-      sT[(e % PWR) * LDP + e / PWR] = a.T[(long)p * PWR * PWR + e];  // T(i, j) at e = i + PWR j
+      sT[(e % PWR) * LDP + e / PWR] = a.T[(long)p * PWR * PWR + e];  // T(i, j) at i + PWR j
     __syncthreads();
-    // partial W(aa, cg) over my rows
-    double pw[PWR];
+    // partial W(aa, c) over my rows: D = A B with A(aa, k) = V(row k, aa), B(k, c) = C(row k, c)
+    dv4 acc[2][2];
 #pragma unroll
-    for (int aa = 0; aa < PWR; ++aa) pw[aa] = 0.0;
+    for (int ab = 0; ab < 2; ++ab)
 #pragma unroll
-    for (int i = 0; i < NR; ++i) {
-      const int r = rg + RG * i;
-      if (r >= p0 && r < d) {
+      for (int cb = 0; cb < 2; ++cb) acc[ab][cb] = dv4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int aa = 0; aa < PWR; ++aa) pw[aa] += sV[r * LDP + aa] * x[i];
+    for (int i = 0; i < NR2; ++i) {
+      const double* vr = sV + (rbase + 16 * i) * LDP;
+      const double a0 = vr[j], a1 = vr[16 + j];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x0[i], acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x1[i], acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x0[i], acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x1[i], acc[1][1], 0, 0, 0);
+    }
+    // D(aa, c) sits in lane c + 16 (aa % 4), register aa / 4
+#pragma unroll
+    for (int ab = 0; ab < 2; ++ab)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr)
+          sWp[(ws * PWR + 16 * ab + 4 * rr + kk) * LDP + 16 * cb + j] = acc[ab][cb][rr];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + NT * q, aa = e / PWR, c = e % PWR;
+      sW[aa * LDP + c] = (sWp[aa * LDP + c] + sWp[(PWR + aa) * LDP + c]) +
+                         (sWp[(2 * PWR + aa) * LDP + c] + sWp[(3 * PWR + aa) * LDP + c]);
+    }
+    __syncthreads();
+    // W' = T^T W: wave ws computes block (ws & 1, ws >> 1)
+    {
+      const int ab = ws & 1, cb = ws >> 1;
+      dv4 t4 = dv4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k0 = 0; k0 < PWR; k0 += 4)
+        t4 = __builtin_amdgcn_mfma_f64_16x16x4f64(sT[(k0 + kk) * LDP + 16 * ab + j],
+                                                  sW[(k0 + kk) * LDP + 16 * cb + j], t4, 0, 0, 0);
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) sW2[(16 * ab + 4 * rr + kk) * LDP + 16 * cb + j] = t4[rr];
+    }
+    __syncthreads();
+    // C -= V W': output rows 16 (i0 + rr) + rbase land in register i0 + rr of this lane
+#pragma unroll
+    for (int i0 = 0; i0 < NR2; i0 += 4) {
+      dv4 u0 = dv4{0.0, 0.0, 0.0, 0.0}, u1 = dv4{0.0, 0.0, 0.0, 0.0};
+      const double* vr = sV + (16 * (i0 + (j >> 2)) + 4 * ws + (j & 3)) * LDP;
+#pragma unroll
+      for (int k0 = 0; k0 < PWR; k0 += 4) {
+        const double av = vr[k0 + kk];
+        u0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, sW2[(k0 + kk) * LDP + j], u0, 0, 0, 0);
+        u1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, sW2[(k0 + kk) * LDP + 16 + j], u1, 0, 0, 0);
       }
-    }
 #pragma unroll
-    for (int aa = 0; aa < PWR; ++aa) pw[aa] += __shfl_xor(pw[aa], 32, 64);
-    if (lane < 32) {
-#pragma unroll
-      for (int aa = 0; aa < PWR; ++aa) sP[(wave * PWR + aa) * LDP + cg] = pw[aa];
-    }
-    __syncthreads();
-    // W(aa, cg) for aa = 4 rg .. 4 rg + 3
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int aa = 4 * rg + q;
-      double t = 0.0;
-#pragma unroll
-      for (int ww = 0; ww < 4; ++ww) t += sP[(ww * PWR + aa) * LDP + cg];
-      sW[aa * LDP + cg] = t;
-    }
-    __syncthreads();
-    // W'(aa, cg) = sum_{t <= aa} T(t, aa) W(t, cg)
-    double w2[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int aa = 4 * rg + q;
-      double t = 0.0;
-      for (int tt = 0; tt <= aa; ++tt) t += sT[tt * LDP + aa] * sW[tt * LDP + cg];
-      w2[q] = t;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) sW[(4 * rg + q) * LDP + cg] = w2[q];
-    __syncthreads();
-    double wv[PWR];
-#pragma unroll
-    for (int aa = 0; aa < PWR; ++aa) wv[aa] = sW[aa * LDP + cg];
-#pragma unroll
-    for (int i = 0; i < NR; ++i) {
-      const int r = rg + RG * i;
-      if (r >= p0 && r < d) {
-        double t = 0.0;
-#pragma unroll
-        for (int aa = 0; aa < PWR; ++aa) t += sV[r * LDP + aa] * wv[aa];
-        x[i] -= t;
+      for (int rr = 0; rr < 4; ++rr) {
+        x0[i0 + rr] -= u0[rr];
+        x1[i0 + rr] -= u1[rr];
       }
     }
     __syncthreads();
@@ -431,43 +441,58 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(HeadArgs a) {
 
   // ---- factor my panel ----
   // Columns stay unscaled while the panel is factored (x_j below row rj; the
-  // reflector is v_j = x_j / (alpha_j - beta_j)); the Gram entries
-  // G(i, j) = v_i^T v_j come out of the same fused reduction and give T at
-  // the end by the UT transform T^{-1} = diag(1/tau) + striu(G).
-  for (int j = 0; j < ncol; ++j) {
-    const int rj = c0 + j;
-    const int buf = j & 1;
-    // broadcast column j inside each wave (writer and readers share the wave)
-    if (cg == j) {
+  // reflector is v_j = x_j / (alpha_j - beta_j)).
+  for (int jc = 0; jc < ncol; ++jc) {
+    const int rj = c0 + jc;
+    const int buf = jc & 1;
+    const bool hi = jc >= 16;
+    const int ir = rj >> 4;                  // register of row rj
+    const bool holder = (rbase == (rj & 15)); // my lane holds row rj
+    if (j == (jc & 15)) {
 #pragma unroll
-      for (int i = 0; i < NR; ++i) {
-        const int r = rg + RG * i;
-        if (r < d) sXb[r] = x[i];
+      for (int i = 0; i < NR2; ++i) sXb[rbase + 16 * i] = hi ? x1[i] : x0[i];
+    }
+    wave_lds_sync();
+    double xj[NR2];
+    double s0a = 0.0, s0b = 0.0, s1a = 0.0, s1b = 0.0;
+#pragma unroll
+    for (int i = 0; i < NR2; ++i) {
+      const double v = sXb[rbase + 16 * i];
+      xj[i] = (rbase + 16 * i > rj) ? v : 0.0;
+      if (i & 1) {
+        s0b = fma(xj[i], x0[i], s0b);
+        s1b = fma(xj[i], x1[i], s1b);
+      } else {
+        s0a = fma(xj[i], x0[i], s0a);
+        s1a = fma(xj[i], x1[i], s1a);
       }
     }
-    double xj[NR];
-    double sacc = 0.0;
-#pragma unroll
-    for (int i = 0; i < NR; ++i) {
-      const int r = rg + RG * i;
-      xj[i] = (r > rj && r < d) ? sXb[r] : 0.0;
-      sacc += xj[i] * x[i];
+    double s0 = s0a + s0b, s1 = s1a + s1b;
+    s0 += __shfl_xor(s0, 16, 64);
+    s1 += __shfl_xor(s1, 16, 64);
+    s0 += __shfl_xor(s0, 32, 64);
+    s1 += __shfl_xor(s1, 32, 64);
+    wave_lds_sync();  // this step's reads of sXb before the next step's writes
+    if (kk == 0) {
+      sRed[(buf * 4 + ws) * PWR + j] = s0;
+      sRed[(buf * 4 + ws) * PWR + 16 + j] = s1;
     }
-    sacc += __shfl_xor(sacc, 32, 64);
-    if (lane < 32) sRed[(buf * 4 + wave) * PWR + cg] = sacc;
-    if (rg == (rj & 7)) {
+    double r0 = 0.0, r1 = 0.0;  // my columns' entries in row rj (meaningful in the holder)
 #pragma unroll
-      for (int i = 0; i < NR; ++i)
-        if (i == (rj >> 3)) sRowJ[buf * PWR + cg] = x[i];
+    for (int i = 0; i < NR2; ++i) {
+      r0 = (i == ir) ? x0[i] : r0;
+      r1 = (i == ir) ? x1[i] : r1;
+    }
+    if (holder) {
+      sRowJ[buf * PWR + j] = r0;
+      sRowJ[buf * PWR + 16 + j] = r1;
     }
     __syncthreads();
-    double S = 0.0, xx = 0.0;
-#pragma unroll
-    for (int ww = 0; ww < 4; ++ww) {
-      S += sRed[(buf * 4 + ww) * PWR + cg];
-      xx += sRed[(buf * 4 + ww) * PWR + j];
-    }
-    const double alpha = sRowJ[buf * PWR + j];
+    const double* red = sRed + buf * 4 * PWR;
+    const double S0 = (red[j] + red[PWR + j]) + (red[2 * PWR + j] + red[3 * PWR + j]);
+    const double S1 = (red[16 + j] + red[PWR + 16 + j]) + (red[2 * PWR + 16 + j] + red[3 * PWR + 16 + j]);
+    const double xx = (red[jc] + red[PWR + jc]) + (red[2 * PWR + jc] + red[3 * PWR + jc]);
+    const double alpha = sRowJ[buf * PWR + jc];
     double beta = alpha, tau = 0.0, inv = 1.0;
     if (xx != 0.0) {
       const double nrm = sqrt(alpha * alpha + xx);
@@ -475,31 +500,36 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(HeadArgs a) {
       tau = (beta - alpha) / beta;
       inv = alpha - beta;
     }
-    if (colok && cg > j) {
-      if (tau != 0.0) {
-        const double wc = sRowJ[buf * PWR + cg] + S / inv;
-        const double f = tau * wc;
-        const double fv = f / inv;
+    if (tau != 0.0) {
+      // the reflector acts on my columns to the right of jc
+      const bool u0c = j > jc && j < ncol, u1c = 16 + j > jc && 16 + j < ncol;
+      const double f0 = u0c ? tau * (sRowJ[buf * PWR + j] + S0 / inv) : 0.0;
+      const double f1 = u1c ? tau * (sRowJ[buf * PWR + 16 + j] + S1 / inv) : 0.0;
+      const double fv0 = f0 / inv, fv1 = f1 / inv;
+      const double fr0 = holder ? f0 : 0.0, fr1 = holder ? f1 : 0.0;
 #pragma unroll
-        for (int i = 0; i < NR; ++i) x[i] -= fv * xj[i];   // xj is 0 at and above row rj
-        if (rg == (rj & 7)) {
-#pragma unroll
-          for (int i = 0; i < NR; ++i)
-            if (i == (rj >> 3)) x[i] -= f;
-        }
+      for (int i = 0; i < NR2; ++i) {  // xj is 0 at and above row rj
+        x0[i] -= fv0 * xj[i] + ((i == ir) ? fr0 : 0.0);
+        x1[i] -= fv1 * xj[i] + ((i == ir) ? fr1 : 0.0);
       }
-    } else if (cg == j && rg == (rj & 7)) {
-#pragma unroll
-      for (int i = 0; i < NR; ++i)
-        if (i == (rj >> 3)) x[i] = beta;
     }
-    // G(i, j) = v_i^T v_j = (x_i(rj) + S_i / inv_j) / inv_i for i < j
+    if (holder && j == (jc & 15)) {
+#pragma unroll
+      for (int i = 0; i < NR2; ++i) {
+        if (!hi) x0[i] = (i == ir) ? beta : x0[i];
+        else x1[i] = (i == ir) ? beta : x1[i];
+      }
+    }
+    // G(i, jc) = v_i^T v_jc = (x_i(rj) + S_i / inv_jc) / inv_i for i < jc
     if (tid < PWR) {
       const int i = tid;
-      if (i < j) sG[i * LDP + j] = (sRowJ[buf * PWR + i] + S / inv) / sInv[i];
+      if (i < jc) {
+        const double Si = (red[i] + red[PWR + i]) + (red[2 * PWR + i] + red[3 * PWR + i]);
+        sG[i * LDP + jc] = (sRowJ[buf * PWR + i] + Si / inv) / sInv[i];
+      }
       if (i == 0) {
-        sTau[j] = tau;
-        sInv[j] = inv;
+        sTau[jc] = tau;
+        sInv[jc] = inv;
         a.tau[rj] = tau;
       }
     }
@@ -509,19 +539,21 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(HeadArgs a) {
   // ---- T of the panel: invert diag(1/tau) + striu(G) (a zero tau decouples
   // its index: its row and column of T are zero) ----
   if (tid < 64) {
-    double tx[W32], ty[W32];
+    if (lane < PWR) {
 #pragma unroll
-    for (int r = 0; r < W32; ++r) {
-      double v = 0.0;
-      if (lane < ncol && r < ncol) {
-        const double tr = sTau[r], tc = sTau[lane];
-        if (tr == 0.0 || tc == 0.0) v = (r == lane) ? 1.0 : 0.0;
-        else if (r == lane) v = 1.0 / tc;
-        else if (r < lane) v = sG[r * LDP + lane];
+      for (int r = 0; r < W32; ++r) {
+        double v = 0.0;
+        if (lane < ncol && r < ncol && r <= lane) {
+          const double tr = sTau[r], tc = sTau[lane];
+          if (tr == 0.0 || tc == 0.0) v = (r == lane) ? 1.0 : 0.0;
+          else if (r == lane) v = 1.0 / tc;
+          else v = sG[r * LDP + lane];
+        }
+        sG[r * LDP + lane] = v;
       }
-      tx[r] = v;
     }
-    wave_inv_upper32_col(tx, ty, ncol);
+    double ty[W32];
+    wave_inv_upper32(sG, LDP, ty, ncol);
     if (lane < PWR) {
 #pragma unroll
       for (int r = 0; r < W32; ++r) {
@@ -534,15 +566,20 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(HeadArgs a) {
   __syncthreads();
 
   // ---- publish V (clean, scaled), R, T ----
-  if (colok) {
-    const int rc = c0 + cg;
-    const double iv = sInv[cg];
 #pragma unroll
-    for (int i = 0; i < NR; ++i) {
-      const int r = rg + RG * i;
-      if (r < d) {
-        a.V[r + (long)rc * d] = (r < rc) ? 0.0 : (r == rc ? 1.0 : x[i] / iv);
-        a.R[r + (long)rc * a.ldr] = (r <= rc) ? x[i] : 0.0;
+  for (int h = 0; h < 2; ++h) {
+    const int cl = 16 * h + j;
+    if (cl < ncol) {
+      const int rc = c0 + cl;
+      const double iv = sInv[cl];
+#pragma unroll
+      for (int i = 0; i < NR2; ++i) {
+        const int r = rbase + 16 * i;
+        const double v = h ? x1[i] : x0[i];
+        if (r < d) {
+          a.V[r + (long)rc * d] = (r < rc) ? 0.0 : (r == rc ? 1.0 : v / iv);
+          a.R[r + (long)rc * a.ldr] = (r <= rc) ? v : 0.0;
+        }
       }
     }
   }
@@ -607,11 +644,13 @@ int run_sketch_qr(const double* B, int d, i64 ni, i64 ldb, double* R, i64 ldr, v
   HeadArgs args{B, (long)ldb, d, dh, pw, R, (long)ldr, V, tau, Tp, flags, status_dev};
   void* params[] = {&args};
   if (d <= 320) {
-    const size_t smem_r = ((size_t)d * LDP + 4 * PWR * LDP + 2 * PWR * LDP + d + 8 * PWR + 2 * PWR +
-                           PWR * LDP + 2 * PWR) * 8;
-    const void* fr = d <= 80 ? (const void*)sketch_head_reg_kernel<10>
-                   : d <= 160 ? (const void*)sketch_head_reg_kernel<20>
-                              : (const void*)sketch_head_reg_kernel<40>;
+    const int nr2 = d <= 128 ? 8 : (d <= 192 ? 12 : 20);
+    const size_t dp = (size_t)16 * nr2;
+    const size_t smem_r = (dp * LDP + 4 * PWR * LDP + 3 * PWR * LDP + dp + 8 * PWR + 2 * PWR +
+                           2 * PWR) * 8;
+    const void* fr = nr2 == 8 ? (const void*)sketch_head_reg_kernel<8>
+                   : nr2 == 12 ? (const void*)sketch_head_reg_kernel<12>
+                               : (const void*)sketch_head_reg_kernel<20>;
     QRCP_HIP(hipFuncSetAttribute(fr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_r));
     QRCP_TRY(launch_resident(fr, dim3(np), dim3(NT), params, smem_r, st));
   } else {
