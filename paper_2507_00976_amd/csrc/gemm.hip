@@ -86,7 +86,25 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WGM, wn = wave / WGM;
-  const int i0 = blockIdx.y * BM, j0 = blockIdx.x * BN;
+  // Tile order.  Workgroups are dispatched round-robin over the 8 XCDs, each
+  // with its own L2: consecutive dispatch slots go to the same XCD's
+  // contiguous range of tiles, and inside a range tiles run in groups of 8
+  // tile rows, so the tiles that are in flight together share their rows of
+  // op(A) and columns of op(B) in one L2.  A permutation of the tiles: the
+  // result does not depend on it.
+  int ti, tj;
+  {
+    const int tn = gridDim.x, tm = gridDim.y, nt = tn * tm;
+    const int b = blockIdx.y * tn + blockIdx.x;
+    const int per = nt / 8;
+    const int L = (b < 8 * per) ? (b % 8) * per + b / 8 : b;
+    constexpr int GM = 8;
+    const int grp = L / (GM * tn), first = grp * GM, rows = min(GM, tm - first);
+    const int in = L - grp * GM * tn;
+    ti = first + in % rows;
+    tj = in / rows;
+  }
+  const int i0 = ti * BM, j0 = tj * BN;
   const int M = g.M, N = g.N;
   const long kbeg = (long)blockIdx.z * g.kchunk;
   const long kend = min((long)g.K, kbeg + g.kchunk);
