@@ -222,11 +222,11 @@ GemmArgs ga(int M, int N, int K, const double* A, i64 lda, const double* B, i64 
   return g;
 }
 
-// (H_0..H_{k-1})^T C for a clean unit lower trapezoidal Y (mi x k, ldy):
-// T from the UT transform of Y^T Y, then W = Y^T C, W2 = T^T W, C -= Y W2.
-int apply_qt_clean(const double* Y, i64 mi, int k, i64 ldy, const double* tau, double* C, i64 nc,
-                   i64 ldc, Prec prec, double* G, double* T, i64 ldk, double* W, double* W2,
-                   double* split, size_t split_bytes, hipStream_t st) {
+// First half of (H_0..H_{k-1})^T C for a clean unit lower trapezoidal Y
+// (mi x k, ldy): T from the UT transform of Y^T Y, W = Y^T C, W2 = T^T W.
+int apply_qt_w(const double* Y, i64 mi, int k, i64 ldy, const double* tau, const double* C,
+               i64 nc, i64 ldc, Prec prec, double* G, double* T, i64 ldk, double* W, double* W2,
+               double* split, size_t split_bytes, hipStream_t st) {
   if (k <= 0 || nc <= 0 || mi <= 0) return QRCP_OK;
   {
     ProfScope ps(kStLarft, 2.0 * mi * k * k, st);
@@ -242,14 +242,74 @@ int apply_qt_clean(const double* Y, i64 mi, int k, i64 ldy, const double* tau, d
     QRCP_TRY(gemm(true, false, prec, w, split, split_bytes, st));
     QRCP_TRY(gemm(true, false, prec, ga(k, (int)nc, k, T, ldk, W, k, W2, k), split, split_bytes, st));
   }
-  {
-    ProfScope ps(kStTrailUpdate, 2.0 * mi * k * nc, st);
-    GemmArgs u = ga((int)mi, (int)nc, k, Y, ldy, W2, k, C, ldc, -1.0, 1.0);
-    u.kind = GemmKind::TrailingUpdate;
-    QRCP_TRY(gemm(false, false, prec, u, nullptr, 0, st));
-  }
   return QRCP_OK;
 }
+
+// Second half, rows r0 .. r1 of C: C(r0:r1, :) -= Y(r0:r1, :) W2.
+int apply_qt_rows(const double* Y, i64 r0, i64 r1, int k, i64 ldy, double* C, i64 nc, i64 ldc,
+                  Prec prec, const double* W2, hipStream_t st) {
+  if (k <= 0 || nc <= 0 || r1 <= r0) return QRCP_OK;
+  ProfScope ps(kStTrailUpdate, 2.0 * (r1 - r0) * k * nc, st);
+  GemmArgs u = ga((int)(r1 - r0), (int)nc, k, Y + r0, ldy, W2, k, C + r0, ldc, -1.0, 1.0);
+  u.kind = GemmKind::TrailingUpdate;
+  QRCP_TRY(gemm(false, false, prec, u, nullptr, 0, st));
+  return QRCP_OK;
+}
+
+int apply_qt_clean(const double* Y, i64 mi, int k, i64 ldy, const double* tau, double* C, i64 nc,
+                   i64 ldc, Prec prec, double* G, double* T, i64 ldk, double* W, double* W2,
+                   double* split, size_t split_bytes, hipStream_t st) {
+  QRCP_TRY(apply_qt_w(Y, mi, k, ldy, tau, C, nc, ldc, prec, G, T, ldk, W, W2, split, split_bytes, st));
+  return apply_qt_rows(Y, 0, mi, k, ldy, C, nc, ldc, prec, W2, st);
+}
+
+// A second stream of the calling thread on the current device, with a fork
+// and a join event, for the rank-k update that overlaps the next block's
+// pivot selection.  Created on first use, kept until the thread ends.
+struct AuxStream {
+  int dev = -1;
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  ~AuxStream() {
+    if (s) hipStreamDestroy(s);
+    if (fork) hipEventDestroy(fork);
+    if (join) hipEventDestroy(join);
+  }
+};
+
+int aux_stream(AuxStream** out) {
+  static thread_local AuxStream a;
+  int dev = 0;
+  QRCP_HIP(hipGetDevice(&dev));
+  if (a.dev != dev) {
+    if (a.s) hipStreamDestroy(a.s);
+    if (a.fork) hipEventDestroy(a.fork);
+    if (a.join) hipEventDestroy(a.join);
+    a.s = nullptr;
+    a.fork = a.join = nullptr;
+    a.dev = -1;
+    QRCP_HIP(hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking));
+    QRCP_HIP(hipEventCreateWithFlags(&a.fork, hipEventDisableTiming));
+    QRCP_HIP(hipEventCreateWithFlags(&a.join, hipEventDisableTiming));
+    a.dev = dev;
+  }
+  *out = &a;
+  return QRCP_OK;
+}
+
+// Makes the caller's stream wait for the overlapped update on every exit path.
+struct JoinGuard {
+  hipStream_t st;
+  AuxStream* aux;
+  bool pending = false;
+  int join() {
+    if (!pending) return QRCP_OK;
+    pending = false;
+    QRCP_HIP(hipStreamWaitEvent(st, aux->join, 0));
+    return QRCP_OK;
+  }
+  ~JoinGuard() { join(); }
+};
 
 }  // namespace
 }  // namespace qrcp
@@ -327,6 +387,9 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
   QRCP_TRY(launch_iota(w.inv, n, st));
   QRCP_TRY(zero_int(w.status, st));
 
+  AuxStream* aux = nullptr;
+  QRCP_TRY(aux_stream(&aux));
+  JoinGuard jg{st, aux};
   int cur = 0;
   i64 ell = 0;
   int status = QRCP_OK;
@@ -358,7 +421,8 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
     const double* Rsk = w.sk0 + s * d;
     // 5. tri_rank
     QRCP_TRY(launch_trirank(Rsk, d, kmax, tol, w.ref, w.kdev, st));
-    // 6. place the panel columns (all m rows)
+    // 6. place the panel columns (all m rows): needs the previous block's update
+    QRCP_TRY(jg.join());
     {
       ProfScope ps(kStPerm, 0.0, st);
       QRCP_TRY(launch_place_columns(A, lda, m, s, kmax, w.plan, w.tmp, m, st));
@@ -424,9 +488,16 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
     }
     // 10-11. trailing update of the physical columns s+k .. n-1 (rows s..m-1)
     const i64 nc = n - s - k;
-    QRCP_TRY(apply_qt_clean(w.Y, mi, k, m, tau + s, A + s + (s + k) * lda, nc, lda, tprec, w.Tm,
-                            w.R11inv, b, w.W, w.W2, w.split, kSplitBytes, st));
-    if (k < kmax || c >= n) { ell = s + k; break; }
+    double* Ct = A + s + (s + k) * lda;
+    QRCP_TRY(apply_qt_w(w.Y, mi, k, m, tau + s, Ct, nc, lda, tprec, w.Tm, w.R11inv, b, w.W, w.W2,
+                        w.split, kSplitBytes, st));
+    if (k < kmax || c >= n) {
+      QRCP_TRY(apply_qt_rows(w.Y, 0, mi, k, m, Ct, nc, lda, tprec, w.W2, st));
+      ell = s + k;
+      break;
+    }
+    // rows s .. s+k (R12) now: the sketch update needs them
+    QRCP_TRY(apply_qt_rows(w.Y, 0, k, k, m, Ct, nc, lda, tprec, w.W2, st));
     // 12. sketch update: M^sk(0:b, c:) = Rsk12 - Rsk11 R11^{-1} R12 (R12 read through the map)
     ProfScope psu(kStSketchUpdate, 2.0 * b * b * (n - c), st);
     QRCP_TRY(launch_trinv_upper(Ablk, lda, (int)b, w.R11inv, b, st));
@@ -436,9 +507,17 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
       g.bcol = w.phys[cur] + c;
       QRCP_TRY(gemm(false, false, Prec::F64, g, nullptr, 0, st));
     }
+    // rows s+k .. m on the second stream, overlapping the next block's pivot
+    // selection, sketch QR and tri_rank (which touch only the sketch buffers)
+    QRCP_HIP(hipEventRecord(aux->fork, st));
+    QRCP_HIP(hipStreamWaitEvent(aux->s, aux->fork, 0));
+    QRCP_TRY(apply_qt_rows(w.Y, k, mi, k, m, Ct, nc, lda, tprec, w.W2, aux->s));
+    QRCP_HIP(hipEventRecord(aux->join, aux->s));
+    jg.pending = true;
     s = c;
     ell = s;
   }
+  QRCP_TRY(jg.join());
   if (status == QRCP_OK && ell < std::min(m, n)) {
     QRCP_TRY(launch_fill(tau + ell, 1, std::min(m, n) - ell, 1, 0.0, st));
   }
