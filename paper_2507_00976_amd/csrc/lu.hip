@@ -265,6 +265,18 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
         uint64_t bk = NOCAND;
         double hx[GQ], hl[GQ], hr[GQ];
         bool badseen = false;
+        // every record this lane reads is requested before the first wait, so
+        // the headers cost one memory round trip whatever G is
+        uint64_t hdr[GQ][HW];
+#pragma unroll
+        for (int qq = 0; qq < GQ; ++qq) {
+          const int gg = lane + 64 * qq;
+          if (gg < G && !to) {
+            uint64_t* r = a.rec + ((long)j * G + gg) * RW;
+#pragma unroll
+            for (int i = 0; i < HW; ++i) hdr[qq][i] = load_agent(r + i);
+          }
+        }
 #pragma unroll
         for (int qq = 0; qq < GQ; ++qq) {
           hx[qq] = 0.0;
@@ -273,9 +285,7 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
           const int gg = lane + 64 * qq;
           if (gg < G && !to) {
             uint64_t* r = a.rec + ((long)j * G + gg) * RW;
-            uint64_t w[HW];
-#pragma unroll
-            for (int i = 0; i < HW; ++i) w[i] = load_agent(r + i);
+            uint64_t (&w)[HW] = hdr[qq];
             long spins = 0;
             for (;;) {
               bool miss = false;

@@ -5,6 +5,7 @@
 // Cholesky step, error status), so the host knows the block rank k before it
 // enqueues the k-dependent launches of the block.
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -240,17 +241,19 @@ int apply_qt_w(const double* Y, i64 mi, int k, i64 ldy, const double* tau, const
     GemmArgs w = ga(k, (int)nc, (int)mi, Y, ldy, C, ldc, W, k);
     w.kind = GemmKind::TrailingW;
     QRCP_TRY(gemm(true, false, prec, w, split, split_bytes, st));
-    QRCP_TRY(gemm(true, false, prec, ga(k, (int)nc, k, T, ldk, W, k, W2, k), split, split_bytes, st));
+    // W2 = -T^T W, so that the update is C += Y W2 (accumulated onto C)
+    QRCP_TRY(gemm(true, false, prec, ga(k, (int)nc, k, T, ldk, W, k, W2, k, -1.0, 0.0), split,
+                  split_bytes, st));
   }
   return QRCP_OK;
 }
 
-// Second half, rows r0 .. r1 of C: C(r0:r1, :) -= Y(r0:r1, :) W2.
+// Second half, rows r0 .. r1 of C: C(r0:r1, :) += Y(r0:r1, :) W2 (W2 = -T^T Y^T C).
 int apply_qt_rows(const double* Y, i64 r0, i64 r1, int k, i64 ldy, double* C, i64 nc, i64 ldc,
                   Prec prec, const double* W2, hipStream_t st) {
   if (k <= 0 || nc <= 0 || r1 <= r0) return QRCP_OK;
   ProfScope ps(kStTrailUpdate, 2.0 * (r1 - r0) * k * nc, st);
-  GemmArgs u = ga((int)(r1 - r0), (int)nc, k, Y + r0, ldy, W2, k, C + r0, ldc, -1.0, 1.0);
+  GemmArgs u = ga((int)(r1 - r0), (int)nc, k, Y + r0, ldy, W2, k, C + r0, ldc, 1.0, 1.0);
   u.kind = GemmKind::TrailingUpdate;
   QRCP_TRY(gemm(false, false, prec, u, nullptr, 0, st));
   return QRCP_OK;
@@ -508,7 +511,14 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
       QRCP_TRY(gemm(false, false, Prec::F64, g, nullptr, 0, st));
     }
     // rows s+k .. m on the second stream, overlapping the next block's pivot
-    // selection, sketch QR and tri_rank (which touch only the sketch buffers)
+    // selection, sketch QR and tri_rank (which touch only the sketch buffers);
+    // QRCP_NO_LOOKAHEAD=1 keeps them on the caller's stream (diagnosis)
+    if (getenv("QRCP_NO_LOOKAHEAD")) {
+      QRCP_TRY(apply_qt_rows(w.Y, k, mi, k, m, Ct, nc, lda, tprec, w.W2, st));
+      s = c;
+      ell = s;
+      continue;
+    }
     QRCP_HIP(hipEventRecord(aux->fork, st));
     QRCP_HIP(hipStreamWaitEvent(aux->s, aux->fork, 0));
     QRCP_TRY(apply_qt_rows(w.Y, k, mi, k, m, Ct, nc, lda, tprec, w.W2, aux->s));

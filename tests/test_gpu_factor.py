@@ -128,3 +128,4 @@ def test_geqrf_matches_oracle(Q, m, n, nb):
     assert np.max(np.abs(np.triu(got) - np.triu(ref))) <= 1e-12 * np.linalg.norm(a)
     np.testing.assert_allclose(tau.cpu().numpy(), tau_ref, rtol=1e-10)
     assert np.max(np.abs(np.tril(got, -1) - np.tril(ref, -1))) <= 1e-10
+
