@@ -52,6 +52,63 @@ def measured_traffic():
     return rec["hbm_bytes_per_launch"] if rec.get("gemm_source_sha256") == sha else None
 
 
+def _counter_rows(path, counter):
+    """(dispatch id, kernel name, value in KiB) of one counter from a rocprofv3
+    counter-collection CSV, values of the same dispatch summed."""
+    import csv
+    out = {}
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            low = {k.lower(): v for k, v in row.items() if k}
+            if low.get("counter_name") != counter:
+                continue
+            did = int(low.get("dispatch_id") or low.get("correlation_id"))
+            name = low.get("kernel_name", "")
+            val = float(low["counter_value"])
+            prev = out.get(did, (name, 0.0))
+            out[did] = (name, prev[1] + val)
+    return [(d, n, v) for d, (n, v) in sorted(out.items())]
+
+
+def write_traffic(fetch_csv, write_csv, n):
+    """Turns a FETCH_SIZE and a WRITE_SIZE counter run of `bench.py --steps 1
+    --warmup 0 --matrix gaussian --no-check` into the HBM bytes per launch of
+    the trailing-update kernel.  Each counter is calibrated with the largest
+    device-to-device copy of the run (the restore of the n x n input, 8 n^2
+    bytes read and written)."""
+    import hashlib
+    res = {}
+    copy_kib = 8.0 * n * n / 1024.0
+    for key, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        rows = _counter_rows(path, counter)
+        copies = [v for _, name, v in rows if "copyBuffer" in name]
+        tu = [v for _, name, v in rows if "trailing_update_kernel" in name]
+        if not copies or not tu:
+            raise SystemExit(f"{path}: no copy or trailing-update dispatches with {counter}")
+        scale = copy_kib / max(copies)
+        res[key] = (sum(tu) / len(tu), scale, len(tu), max(tu))
+    with open(os.path.join(ROOT, "paper_2507_00976_amd", "csrc", "gemm.hip"), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    fk, fs, nl, fmax = res["fetch"]
+    wk, ws, _, wmax = res["write"]
+    rec = {
+        "kernel": "trailing_update_kernel",
+        "workload": f"qrcp {n}x{n} b=256 d=320 (Gaussian input, same launch sizes)",
+        "launches": nl,
+        "fetch_kib_per_launch": round(fk, 1),
+        "write_kib_per_launch": round(wk, 1),
+        "fetch_scale": round(fs, 5),
+        "write_scale": round(ws, 5),
+        "hbm_bytes_per_launch": int(round((fk * fs + wk * ws) * 1024.0)),
+        "largest_launch_hbm_bytes": int(round((fmax * fs + wmax * ws) * 1024.0)),
+        "gemm_source_sha256": sha,
+    }
+    out = os.path.join(ROOT, "profiles", "trailing_update_kernel_16384_traffic.json")
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
 def canonical_flops(m, n):
     return 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
 
@@ -318,11 +375,17 @@ def main():
                          "counter runs)")
     ap.add_argument("--no-check", action="store_true",
                     help="skip the sampled residual check (it calls library GEMM/inverse)")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no benchmark: turn two rocprofv3 counter-collection CSVs (FETCH_SIZE, "
+                         "WRITE_SIZE) of a Gaussian-input run into the committed traffic record")
     args = ap.parse_args()
 
+    if args.write_traffic:
+        write_traffic(args.write_traffic[0], args.write_traffic[1], args.n)
+        return
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "a multi-GPU sharding of the method is not built.",
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the method is "
+              "not sharded over several GPUs here.",
               file=sys.stderr)
         sys.exit(2)
 

