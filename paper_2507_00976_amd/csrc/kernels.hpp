@@ -46,6 +46,16 @@ int launch_potrf_upper(double* G, i64 ldg, int n, int* info_dev, hipStream_t st)
 // Sign-modified LU without pivoting of the k x k head of Q (reconstruction):
 // overwrites Q(0:k,0:k) with Y1 (strict lower) and U (upper); dsig[k].
 int launch_headlu(double* Q, i64 ldq, int k, double* dsig, hipStream_t st);
+// The same two factorizations over resident workgroups (one per 32 x 32
+// block) for orders up to 256, given blockfact_scratch_bytes() of scratch;
+// otherwise (or with QRCP_SMALLFACT=single) the single-workgroup kernels.
+// potrf: info < 0 after a timeout; headlu: *status = QRCP_ERR_TIMEOUT.
+size_t blockfact_scratch_bytes();
+int blockfact_groups(int n);
+int launch_potrf_mw(double* G, i64 ldg, int n, int* info_dev, void* scratch, size_t scratch_bytes,
+                    hipStream_t st);
+int launch_headlu_mw(double* Q, i64 ldq, int k, double* dsig, void* scratch, size_t scratch_bytes,
+                     int* status, hipStream_t st);
 // tau_j = -dsig_j U(j,j)
 int launch_tau_from_u(const double* Q, i64 ldq, int k, const double* dsig, double* tau,
                       hipStream_t st);

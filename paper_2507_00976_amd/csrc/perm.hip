@@ -22,9 +22,13 @@ __global__ __launch_bounds__(1024) void perm_plan_kernel(const long* jsk, long s
                                                         const long* phys0, long* phys1, long* inv,
                                                         long* plan) {
   extern __shared__ long sm[];
-  long* src = sm;              // kmax
-  int* mark = (int*)(sm + kmax);
-  const int tid = threadIdx.x;
+  long* src = sm;              // kmax: physical column of panel slot t
+  long* dsl = src + kmax;      // kmax: displaced slots, in increasing order
+  long* fsl = dsl + kmax;      // kmax: free slots, in panel-slot order
+  int* mark = (int*)(fsl + kmax);
+  __shared__ int wcnt[2][16];
+  __shared__ int base[2];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const long ni = n - s;
   const long c = s + kmax;
   for (long p = tid; p < s; p += blockDim.x) {
@@ -39,6 +43,7 @@ __global__ __launch_bounds__(1024) void perm_plan_kernel(const long* jsk, long s
   __syncthreads();
   for (long p = s + tid; p < n; p += blockDim.x) inv[phys1[p]] = p;
   for (int t = tid; t < kmax; t += blockDim.x) mark[t] = 0;
+  if (tid == 0) base[0] = base[1] = 0;
   __syncthreads();
   for (int t = tid; t < kmax; t += blockDim.x) {
     src[t] = phys1[s + t];
@@ -46,20 +51,47 @@ __global__ __launch_bounds__(1024) void perm_plan_kernel(const long* jsk, long s
     if (src[t] < c) mark[src[t] - s] = 1;
   }
   __syncthreads();
-  if (tid == 0) {
-    long nd = 0, nf = 0;
-    for (int x = 0; x < kmax; ++x)
-      if (!mark[x]) plan[8 + kmax + nd++] = s + x;
-    for (int t = 0; t < kmax; ++t)
-      if (src[t] >= c) plan[8 + 2 * kmax + nf++] = src[t];
-    plan[0] = nd;
-    // displaced logical columns take the free slots
-    for (long q = 0; q < nd; ++q) {
-      const long dslot = plan[8 + kmax + q], fslot = plan[8 + 2 * kmax + q];
-      const long lg = inv[dslot];
-      phys1[lg] = fslot;
-      inv[fslot] = lg;
+  // stable compactions (ballot ranks within a wave, wave counts through LDS):
+  // D = unmarked panel slots in increasing order, F = sources beyond the panel
+  // in panel-slot order
+  const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (int x0 = 0; x0 < kmax; x0 += blockDim.x) {
+    const int x = x0 + tid;
+    const bool fd = x < kmax && !mark[x];
+    const bool ff = x < kmax && src[x] >= c;
+    const unsigned long long bd = __ballot(fd), bf = __ballot(ff);
+    if (lane == 0) {
+      wcnt[0][wave] = __popcll(bd);
+      wcnt[1][wave] = __popcll(bf);
     }
+    __syncthreads();
+    int od = base[0], of = base[1];
+    for (int w = 0; w < wave; ++w) {
+      od += wcnt[0][w];
+      of += wcnt[1][w];
+    }
+    if (fd) dsl[od + __popcll(bd & below)] = s + x;
+    if (ff) fsl[of + __popcll(bf & below)] = src[x];
+    __syncthreads();
+    if (tid == 0) {
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        base[0] += wcnt[0][w];
+        base[1] += wcnt[1][w];
+      }
+    }
+    __syncthreads();
+  }
+  const int nd = base[0];  // equals the number of free slots
+  if (tid == 0) plan[0] = nd;
+  // displaced logical columns take the free slots; the displaced slots lie in
+  // [s, c) and the free ones at c or beyond, so the pairs are independent
+  for (int q = tid; q < nd; q += blockDim.x) {
+    const long dslot = dsl[q], fslot = fsl[q];
+    plan[8 + kmax + q] = dslot;
+    plan[8 + 2 * kmax + q] = fslot;
+    const long lg = inv[dslot];
+    phys1[lg] = fslot;
+    inv[fslot] = lg;
   }
   __syncthreads();
   for (int t = tid; t < kmax; t += blockDim.x) {
@@ -70,7 +102,8 @@ __global__ __launch_bounds__(1024) void perm_plan_kernel(const long* jsk, long s
 
 int launch_perm_plan(const i64* jsk, i64 s, i64 n, int kmax, const i64* J0, i64* J1,
                      const i64* phys0, i64* phys1, i64* inv, i64* plan, hipStream_t st) {
-  const size_t smem = (size_t)kmax * 8 + (size_t)kmax * 4 + 16;
+  const size_t smem = (size_t)kmax * 8 * 3 + (size_t)kmax * 4 + 16;
+  if (smem > 64 * 1024) return QRCP_ERR_UNSUPPORTED;
   hipLaunchKernelGGL(perm_plan_kernel, dim3(1), dim3(1024), smem, st, (const long*)jsk, s, n, kmax,
                      (const long*)J0, (long*)J1, (const long*)phys0, (long*)phys1, (long*)inv,
                      (long*)plan);

@@ -440,12 +440,13 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
       // 8. Gram and Cholesky; a breakdown (or the rank cut) ends the factor at info
       QRCP_TRY(gemm(true, false, Prec::F64, ga(kmax, kmax, (int)mi, w.Y, m, w.Y, m, w.G, b), w.split,
                     kSplitBytes, st));
-      QRCP_TRY(launch_potrf_upper(w.G, b, kmax, w.info, st));
+      QRCP_TRY(launch_potrf_mw(w.G, b, kmax, w.info, w.split, kSplitBytes, st));
     }
     int hs[3];
     QRCP_HIP(hipMemcpyAsync(hs, w.status, sizeof(int), hipMemcpyDeviceToHost, st));
     QRCP_TRY(read_back(hs + 1, w.info, sizeof(int), st));
     if (hs[0] != QRCP_OK) { status = hs[0]; ell = s; break; }
+    if (hs[1] < 0) { status = QRCP_ERR_TIMEOUT; ell = s; break; }
     int k = hs[1];
     if (k == 0) { ell = s; break; }
     // Q = M^pre Rc^{-1}
@@ -455,8 +456,9 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
     if (o.cholqr_passes == 2) {
       QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, k, k, w.Y, m, w.Rinv, b, w.tmp, m), nullptr, 0, st));
       QRCP_TRY(gemm(true, false, Prec::F64, ga(k, k, (int)mi, w.tmp, m, w.tmp, m, w.R2, b), w.split, kSplitBytes, st));
-      QRCP_TRY(launch_potrf_upper(w.R2, b, k, w.info, st));
+      QRCP_TRY(launch_potrf_mw(w.R2, b, k, w.info, w.split, kSplitBytes, st));
       QRCP_TRY(read_back(hs + 2, w.info, sizeof(int), st));
+      if (hs[2] < 0) { status = QRCP_ERR_TIMEOUT; ell = s; break; }
       if (hs[2] < k) {
         // second pass broke down: keep the columns factored by both passes
         k = hs[2];
@@ -476,7 +478,7 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
     // 9. Householder reconstruction: sign-modified LU of the head, Y2 = Q2 U^{-1}
     {
     ProfScope psr(kStRecon, 2.0 * (mi - k) * k * k + 2.0 * k * k * k, st);
-    QRCP_TRY(launch_headlu(Ablk, lda, k, w.dsig, st));
+    QRCP_TRY(launch_headlu_mw(Ablk, lda, k, w.dsig, w.split, kSplitBytes, w.status, st));
     QRCP_TRY(launch_tau_from_u(Ablk, lda, k, w.dsig, tau + s, st));
     QRCP_TRY(launch_trinv_upper(Ablk, lda, k, w.Uinv, b, st));
     if (mi > k) {
@@ -535,7 +537,9 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
     QRCP_TRY(launch_final_permute(A, lda, m, ell, n, w.phys[cur], w.big, st));
   }
   QRCP_TRY(launch_jpiv_out(w.J[cur], n, o.pivot_base, jpiv, st));
-  QRCP_HIP(hipStreamSynchronize(st));
+  int fin = QRCP_OK;
+  QRCP_TRY(read_back(&fin, w.status, sizeof(int), st));  // a wait that ran out after the last check
+  if (status == QRCP_OK && fin != QRCP_OK) status = fin;
   *rank = ell;
   return status;
 }
@@ -745,9 +749,10 @@ int qrcp_cholqr(double* P, int64_t mi, int64_t k, int64_t ldp, const double* Rs,
   QRCP_TRY(launch_trinv_upper(Rs, ldrs, kk, Rinv, k, st));
   QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, kk, kk, P, ldp, Rinv, k, Mp, mi), nullptr, 0, st));
   QRCP_TRY(gemm(true, false, Prec::F64, ga(kk, kk, (int)mi, Mp, mi, Mp, mi, G, k), split, kSplitBytes, st));
-  QRCP_TRY(launch_potrf_upper(G, k, kk, info, st));
+  QRCP_TRY(launch_potrf_mw(G, k, kk, info, split, kSplitBytes, st));
   int t = 0;
   QRCP_TRY(read_back(&t, info, sizeof(int), st));
+  if (t < 0) return QRCP_ERR_TIMEOUT;
   if (t < kk) {
     *keff = t;
     QRCP_TRY(launch_copy2d(G, k, Rc, ldrc, t, t, st));
@@ -758,8 +763,9 @@ int qrcp_cholqr(double* P, int64_t mi, int64_t k, int64_t ldp, const double* Rs,
   if (passes == 2) {
     QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, kk, kk, Mp, mi, Rinv, k, Q1, mi), nullptr, 0, st));
     QRCP_TRY(gemm(true, false, Prec::F64, ga(kk, kk, (int)mi, Q1, mi, Q1, mi, G2, k), split, kSplitBytes, st));
-    QRCP_TRY(launch_potrf_upper(G2, k, kk, info, st));
+    QRCP_TRY(launch_potrf_mw(G2, k, kk, info, split, kSplitBytes, st));
     QRCP_TRY(read_back(&t, info, sizeof(int), st));
+    if (t < 0) return QRCP_ERR_TIMEOUT;
     if (t < kk) {
       *keff = t;
       QRCP_TRY(launch_copy2d(G, k, Rc, ldrc, t, t, st));
@@ -791,16 +797,20 @@ int qrcp_reconstruct(double* Q, int64_t mi, int64_t k, int64_t ldq, double* tau,
   Carver c{(char*)workspace};
   double* Yt = c.take<double>((size_t)mi * k);
   double* Uinv = c.take<double>((size_t)k * k);
+  int* stat = c.take<int>(4);
+  double* scratch = c.take<double>(kSplitBytes / 8);
   const int kk = (int)k;
-  QRCP_TRY(launch_headlu(Q, ldq, kk, dsig, st));
+  QRCP_TRY(zero_int(stat, st));
+  QRCP_TRY(launch_headlu_mw(Q, ldq, kk, dsig, scratch, kSplitBytes, stat, st));
   QRCP_TRY(launch_tau_from_u(Q, ldq, kk, dsig, tau, st));
   QRCP_TRY(launch_trinv_upper(Q, ldq, kk, Uinv, k, st));
   if (mi > k) {
     QRCP_TRY(gemm(false, false, Prec::F64, ga((int)(mi - k), kk, kk, Q + k, ldq, Uinv, k, Yt, mi), nullptr, 0, st));
     QRCP_TRY(launch_copy2d(Yt, mi, Q + k, ldq, mi - k, k, st));
   }
-  QRCP_HIP(hipStreamSynchronize(st));
-  return QRCP_OK;
+  int fin = QRCP_OK;
+  QRCP_TRY(read_back(&fin, stat, sizeof(int), st));
+  return fin;
 }
 
 size_t qrcp_apply_qt_workspace_size(int64_t mi, int64_t k, int64_t nc) {

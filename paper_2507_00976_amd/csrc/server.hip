@@ -61,7 +61,8 @@ namespace {
 
 int request_groups(const qrcp_request& r) {
   const int d = (int)std::ceil(r.sketch_factor * (double)r.block_size - 1e-12);
-  return std::max(lu_resident_groups(r.n), sketch_head_groups(d, r.n));
+  const int bf = blockfact_groups((int)std::min<int64_t>(r.block_size, r.n));
+  return std::max(std::max(lu_resident_groups(r.n), sketch_head_groups(d, r.n)), bf);
 }
 
 void worker_main(qrcp_server* s, int w) {
