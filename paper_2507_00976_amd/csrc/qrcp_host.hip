@@ -273,11 +273,15 @@ struct AuxStream {
   int dev = -1;
   hipStream_t s = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
-  ~AuxStream() {
+  void release() {
     if (s) hipStreamDestroy(s);
-    if (fork) hipEventDestroy(fork);
-    if (join) hipEventDestroy(join);
+    for (hipEvent_t e : {fork, join})
+      if (e) hipEventDestroy(e);
+    s = nullptr;
+    fork = join = nullptr;
+    dev = -1;
   }
+  ~AuxStream() { release(); }
 };
 
 int aux_stream(AuxStream** out) {
@@ -285,12 +289,7 @@ int aux_stream(AuxStream** out) {
   int dev = 0;
   QRCP_HIP(hipGetDevice(&dev));
   if (a.dev != dev) {
-    if (a.s) hipStreamDestroy(a.s);
-    if (a.fork) hipEventDestroy(a.fork);
-    if (a.join) hipEventDestroy(a.join);
-    a.s = nullptr;
-    a.fork = a.join = nullptr;
-    a.dev = -1;
+    a.release();
     QRCP_HIP(hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking));
     QRCP_HIP(hipEventCreateWithFlags(&a.fork, hipEventDisableTiming));
     QRCP_HIP(hipEventCreateWithFlags(&a.join, hipEventDisableTiming));
@@ -393,6 +392,26 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
   AuxStream* aux = nullptr;
   QRCP_TRY(aux_stream(&aux));
   JoinGuard jg{st, aux};
+  // the previous block's rank-k update of rows s+k .. m, started on the
+  // second stream once the next block's pivots are known
+  struct Pending {
+    bool on = false;
+    i64 r0 = 0, r1 = 0, nc = 0;
+    int k = 0;
+    double* C = nullptr;
+  } pend;
+  auto start_pending = [&]() -> int {
+    if (!pend.on) return QRCP_OK;
+    pend.on = false;
+    if (getenv("QRCP_NO_LOOKAHEAD"))
+      return apply_qt_rows(w.Y, pend.r0, pend.r1, pend.k, m, pend.C, pend.nc, lda, tprec, w.W2, st);
+    QRCP_HIP(hipEventRecord(aux->fork, st));
+    QRCP_HIP(hipStreamWaitEvent(aux->s, aux->fork, 0));
+    QRCP_TRY(apply_qt_rows(w.Y, pend.r0, pend.r1, pend.k, m, pend.C, pend.nc, lda, tprec, w.W2, aux->s));
+    QRCP_HIP(hipEventRecord(aux->join, aux->s));
+    jg.pending = true;
+    return QRCP_OK;
+  };
   int cur = 0;
   i64 ell = 0;
   int status = QRCP_OK;
@@ -414,6 +433,10 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
                                 w.phys[1 - cur], w.inv, w.plan, st));
       QRCP_TRY(launch_sketch_permute(w.sk0 + s * d, w.sk1 + s * d, d, d, ni, w.jsk, st));
     }
+    // The previous block's update runs beside the sketch QR and tri_rank
+    // (which touch only the sketch buffers), not beside the pivot selection,
+    // whose per-step exchange is slowed by the update's memory traffic.
+    QRCP_TRY(start_pending());
     cur = 1 - cur;
     // 4. R factor of the permuted sketch (back into sk0, logical positions)
     {
@@ -512,23 +535,18 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
       g.bcol = w.phys[cur] + c;
       QRCP_TRY(gemm(false, false, Prec::F64, g, nullptr, 0, st));
     }
-    // rows s+k .. m on the second stream, overlapping the next block's pivot
-    // selection, sketch QR and tri_rank (which touch only the sketch buffers);
-    // QRCP_NO_LOOKAHEAD=1 keeps them on the caller's stream (diagnosis)
-    if (getenv("QRCP_NO_LOOKAHEAD")) {
-      QRCP_TRY(apply_qt_rows(w.Y, k, mi, k, m, Ct, nc, lda, tprec, w.W2, st));
-      s = c;
-      ell = s;
-      continue;
-    }
-    QRCP_HIP(hipEventRecord(aux->fork, st));
-    QRCP_HIP(hipStreamWaitEvent(aux->s, aux->fork, 0));
-    QRCP_TRY(apply_qt_rows(w.Y, k, mi, k, m, Ct, nc, lda, tprec, w.W2, aux->s));
-    QRCP_HIP(hipEventRecord(aux->join, aux->s));
-    jg.pending = true;
+    // rows s+k .. m: deferred to the next block, on the second stream
+    // (QRCP_NO_LOOKAHEAD=1 keeps them on the caller's stream, for diagnosis)
+    pend.on = true;
+    pend.r0 = k;
+    pend.r1 = mi;
+    pend.k = k;
+    pend.C = Ct;
+    pend.nc = nc;
     s = c;
     ell = s;
   }
+  QRCP_TRY(start_pending());
   QRCP_TRY(jg.join());
   if (status == QRCP_OK && ell < std::min(m, n)) {
     QRCP_TRY(launch_fill(tau + ell, 1, std::min(m, n) - ell, 1, 0.0, st));
