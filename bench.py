@@ -442,7 +442,7 @@ def main():
     tu_avg_ms = tu_ms / max(tu_cnt, 1)
     tu_tflops = (tu_flops / max(tu_cnt, 1)) / (tu_avg_ms / 1e3) / 1e12 if tu_cnt else 0.0
     roofline = {
-        "kernel": "trailing_update_kernel (C -= Y W, FP64 MFMA)",
+        "kernel": "trailing_update_kernel (C += Y W2, W2 = -T^T Y^T C, FP64 MFMA)",
         "bound": "mfma",
         "achieved": round(tu_tflops, 3),
         "peak": PEAK_FP64_TFLOPS,

@@ -67,7 +67,8 @@ size_t qrcp_workspace_size(int64_t m, int64_t n, int64_t block_size, double sket
  *          when rank < n.
  *  m, n    m >= n >= 0 (m < n returns QRCP_ERR_UNSUPPORTED).
  *  block_size   b >= 1.
- *  sketch_factor gamma >= 1; the sketch has d = ceil(gamma*b) rows.
+ *  sketch_factor gamma >= 1; the sketch has d = ceil(gamma*b) rows
+ *          (d <= 1024 and n <= 65536, else QRCP_ERR_UNSUPPORTED).
  *  seed    key of the Philox4x32-10 stream that draws the Gaussian sketching
  *          operator (Sec. 2: randomness is used once, before the loop).
  *  tol     >= 0; block rank = leading run of |Rsk(t,t)| > tol * (largest
@@ -233,7 +234,7 @@ void qrcp_server_destroy(qrcp_server* s);
 
 /* ------------------------------------------------------------------------
  * Stage timing (instrumentation, not part of the method).  mode 0 = off,
- * 1 = time only the trailing-update product C -= Y W (the dominant kernel),
+ * 1 = time only the trailing-update product C += Y W2 (the dominant kernel),
  * 2 = time every stage of the loop.  Enabling clears earlier records.  HIP
  * events are recorded on the stream of each call; qrcp_profile_read() waits
  * for them and returns the summed device time (ms), the number of timed

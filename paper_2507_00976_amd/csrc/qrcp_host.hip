@@ -367,7 +367,7 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
   if (!tau) return -10;
   const i64 b = std::min<i64>(block_size, n);
   const int d = sketch_rows(block_size, sketch_factor);
-  if (d > 1280 || n > 65536) return QRCP_ERR_UNSUPPORTED;
+  if (d > 1024 || n > 65536) return QRCP_ERR_UNSUPPORTED;
   FactorWs w;
   const size_t need = carve_factor(nullptr, m, n, b, d, &w);
   if (!workspace || workspace_bytes < need) return QRCP_ERR_WORKSPACE;

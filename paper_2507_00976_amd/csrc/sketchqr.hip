@@ -233,10 +233,14 @@ __global__ __launch_bounds__(NT) void sketch_head_kernel(HeadArgs a) {
       tau = (beta - alpha) / beta;
       inv = alpha - beta;
     }
-    if (tau != 0.0 && cg > jj && cg < ncol) {
+    // Every thread of column cg reads x_rj(cg) here; the entry itself is
+    // updated only after the barrier below (threads of several waves share a
+    // column, so an earlier write would race with their reads).
+    double f = 0.0;
+    const bool upd = tau != 0.0 && cg > jj && cg < ncol;
+    if (upd) {
       const double wc = sC[cg * ldc + rj] + sW[cg] / inv;
-      const double f = tau * wc;
-      if (rg == 0) sC[cg * ldc + rj] -= f;
+      f = tau * wc;
       const double fv = f / inv;
       for (int r = rj + 1 + rg; r < d; r += RG) sC[cg * ldc + r] -= fv * xj[r];
     }
@@ -247,7 +251,10 @@ __global__ __launch_bounds__(NT) void sketch_head_kernel(HeadArgs a) {
       a.R[rj + (long)rj * a.ldr] = beta;
     }
     __syncthreads();
+    // row rj is read again only by the publication below
+    if (upd && rg == 0) sC[cg * ldc + rj] -= f;
   }
+  __syncthreads();
 
   // ---- publish V_p (clean), R part above the diagonal, and T_p ----
   for (int e = tid; e < PW * d; e += NT) {
@@ -622,7 +629,7 @@ size_t sketch_qr_ws_bytes(int d, i64 ni) {
 int run_sketch_qr(const double* B, int d, i64 ni, i64 ldb, double* R, i64 ldr, void* ws,
                   size_t ws_bytes, int* status_dev, hipStream_t st) {
   if (d <= 0 || ni <= 0) return QRCP_OK;
-  if (d > 1280) return QRCP_ERR_UNSUPPORTED;
+  if (d > 1024) return QRCP_ERR_UNSUPPORTED;  // the tail inverts a dh x dh triangle
   if (ws_bytes < sketch_qr_ws_bytes(d, ni)) return QRCP_ERR_WORKSPACE;
   const int dh = (int)std::min((i64)d, ni);
   const int pw = head_pw(d);

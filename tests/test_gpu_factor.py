@@ -129,3 +129,18 @@ def test_geqrf_matches_oracle(Q, m, n, nb):
     np.testing.assert_allclose(tau.cpu().numpy(), tau_ref, rtol=1e-10)
     assert np.max(np.abs(np.tril(got, -1) - np.tril(ref, -1))) <= 1e-10
 
+
+
+@pytest.mark.parametrize("b", [128, 512])
+def test_lowrank_rank_detection_repeatable(Q, b):
+    """A = G1 G2 + 1e-12 N (exact rank 512 plus noise far below tol): the
+    detected rank is 512 (the oracle agrees), and repeated runs are bitwise
+    identical (b = 512 uses the 640-row sketch and its own head kernel)."""
+    m, r = 2048, 512
+    a = W.lowrank(m, m, r, 1e-12, 20250702)
+    runs = [run_gpu(Q, a, b, 1.25, 42, 1e-10) for _ in range(3)]
+    for got in runs:
+        assert got.rank == r
+        assert np.array_equal(got.jpiv, runs[0].jpiv)
+        assert np.array_equal(got.tau, runs[0].tau)
+        assert np.array_equal(got.a, runs[0].a)

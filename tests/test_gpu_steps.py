@@ -105,6 +105,18 @@ def test_sketch_qr_matches_oracle(Q, d, ni):
     assert np.all(np.tril(got, -1) == 0.0)
 
 
+@pytest.mark.parametrize("d,ni", [(640, 3000), (960, 1200), (400, 2000)])
+def test_sketch_qr_repeatable_wide_sketch(Q, d, ni):
+    # sketches of more than 320 rows use the panel kernel with 16- and 8-wide
+    # panels; repeated runs must be bitwise identical and match the oracle
+    b = W.gaussian(d, ni, seed=3 * d + ni)
+    runs = [host(Q.sketch_qr(dev(b))) for _ in range(3)]
+    for got in runs[1:]:
+        assert np.array_equal(got, runs[0])
+    ref, _, _ = O.householder_qr(b)
+    assert np.max(np.abs(runs[0] - ref)) <= 1e-12 * np.linalg.norm(b)
+
+
 def test_sketch_qr_zero_column(Q):
     # a zero column gives tau = 0 (H_j = I) inside the head and in the tail's T
     b = W.gaussian(40, 90, seed=9)
