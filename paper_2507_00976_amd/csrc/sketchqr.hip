@@ -12,6 +12,8 @@
 // Tail (the remaining ni - dh columns): R_tail = Q^T B_tail with the explicit
 // d x d Q = I - V T V^T, T from the UT transform of V^T V, all on the GEMM
 // kernels.
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "wave32.hpp"
@@ -448,16 +450,52 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(HeadArgs a) {
 
   // ---- factor my panel ----
   // Columns stay unscaled while the panel is factored (x_j below row rj; the
-  // reflector is v_j = x_j / (alpha_j - beta_j)).
-  for (int jc = 0; jc < ncol; ++jc) {
-    const int rj = c0 + jc;
-    const int buf = jc & 1;
-    const bool hi = jc >= 16;
-    const int ir = rj >> 4;                  // register of row rj
-    const bool holder = (rbase == (rj & 15)); // my lane holds row rj
-    if (j == (jc & 15)) {
+  // reflector is v_j = x_j / (alpha_j - beta_j)).  Register i holds row group
+  // sh + i (rows 16 (sh + i) + rbase).  Groups above the pivot row are final:
+  // they are written out (R on and above the diagonal, the scaled reflectors
+  // below it) and shifted away, so the pivot row's group is always register 0
+  // and, with the panel's two 16-column halves as compile-time cases, every
+  // row and column selection below is resolved at compile time.
+  int sh = 0;
+  auto emit = [&](int i, double v0, double v1) {
+    const int r = 16 * (sh + i) + rbase;
+    if (r >= d) return;
 #pragma unroll
-      for (int i = 0; i < NR2; ++i) sXb[rbase + 16 * i] = hi ? x1[i] : x0[i];
+    for (int h = 0; h < 2; ++h) {
+      const int cl = 16 * h + j;
+      if (cl < ncol) {
+        const int rc = c0 + cl;
+        const double v = h ? v1 : v0;
+        a.V[r + (long)rc * d] = (r < rc) ? 0.0 : (r == rc ? 1.0 : v / sInv[cl]);
+        a.R[r + (long)rc * a.ldr] = (r <= rc) ? v : 0.0;
+      }
+    }
+  };
+  auto shift1 = [&]() {
+#pragma unroll
+    for (int i = 0; i + 1 < NR2; ++i) {
+      x0[i] = x0[i + 1];
+      x1[i] = x1[i + 1];
+    }
+    x0[NR2 - 1] = 0.0;
+    x1[NR2 - 1] = 0.0;
+    ++sh;
+  };
+  // rows above the panel: final after the apply phase
+  for (int g = 0; g < (c0 >> 4); ++g) {
+    emit(0, x0[0], x1[0]);
+    shift1();
+  }
+  auto col_step = [&](auto hic, int jc) {
+    constexpr bool HI = decltype(hic)::value;
+    double(&xc)[NR2] = HI ? x1 : x0;  // the half holding column jc
+    const int rj = c0 + jc;
+    const int jl = jc & 15;          // pivot row within its group (register 0)
+    const int buf = jc & 1;
+    const bool holder = (rbase == jl);  // my lane holds row rj
+    if (j == jl) {
+#pragma unroll
+      for (int i = 0; i < NR2; ++i) sXb[rbase + 16 * i] = xc[i];
     }
     wave_lds_sync();
     double xj[NR2];
@@ -465,7 +503,7 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(HeadArgs a) {
 #pragma unroll
     for (int i = 0; i < NR2; ++i) {
       const double v = sXb[rbase + 16 * i];
-      xj[i] = (rbase + 16 * i > rj) ? v : 0.0;
+      xj[i] = (i > 0 || rbase > jl) ? v : 0.0;  // rows below rj only
       if (i & 1) {
         s0b = fma(xj[i], x0[i], s0b);
         s1b = fma(xj[i], x1[i], s1b);
@@ -484,15 +522,9 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(HeadArgs a) {
       sRed[(buf * 4 + ws) * PWR + j] = s0;
       sRed[(buf * 4 + ws) * PWR + 16 + j] = s1;
     }
-    double r0 = 0.0, r1 = 0.0;  // my columns' entries in row rj (meaningful in the holder)
-#pragma unroll
-    for (int i = 0; i < NR2; ++i) {
-      r0 = (i == ir) ? x0[i] : r0;
-      r1 = (i == ir) ? x1[i] : r1;
-    }
     if (holder) {
-      sRowJ[buf * PWR + j] = r0;
-      sRowJ[buf * PWR + 16 + j] = r1;
+      sRowJ[buf * PWR + j] = x0[0];
+      sRowJ[buf * PWR + 16 + j] = x1[0];
     }
     __syncthreads();
     const double* red = sRed + buf * 4 * PWR;
@@ -513,20 +545,15 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(HeadArgs a) {
       const double f0 = u0c ? tau * (sRowJ[buf * PWR + j] + S0 / inv) : 0.0;
       const double f1 = u1c ? tau * (sRowJ[buf * PWR + 16 + j] + S1 / inv) : 0.0;
       const double fv0 = f0 / inv, fv1 = f1 / inv;
-      const double fr0 = holder ? f0 : 0.0, fr1 = holder ? f1 : 0.0;
+      x0[0] -= fv0 * xj[0] + (holder ? f0 : 0.0);
+      x1[0] -= fv1 * xj[0] + (holder ? f1 : 0.0);
 #pragma unroll
-      for (int i = 0; i < NR2; ++i) {  // xj is 0 at and above row rj
-        x0[i] -= fv0 * xj[i] + ((i == ir) ? fr0 : 0.0);
-        x1[i] -= fv1 * xj[i] + ((i == ir) ? fr1 : 0.0);
+      for (int i = 1; i < NR2; ++i) {
+        x0[i] -= fv0 * xj[i];
+        x1[i] -= fv1 * xj[i];
       }
     }
-    if (holder && j == (jc & 15)) {
-#pragma unroll
-      for (int i = 0; i < NR2; ++i) {
-        if (!hi) x0[i] = (i == ir) ? beta : x0[i];
-        else x1[i] = (i == ir) ? beta : x1[i];
-      }
-    }
+    if (holder && j == jl) xc[0] = beta;
     // G(i, jc) = v_i^T v_jc = (x_i(rj) + S_i / inv_jc) / inv_i for i < jc
     if (tid < PWR) {
       const int i = tid;
@@ -540,6 +567,13 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(HeadArgs a) {
         a.tau[rj] = tau;
       }
     }
+  };
+  for (int jc = 0; jc < min(ncol, 16); ++jc) col_step(std::false_type{}, jc);
+  if (ncol > 16) {
+    __syncthreads();  // sInv of the first half
+    emit(0, x0[0], x1[0]);  // rows c0 .. c0+15: final for the whole panel
+    shift1();
+    for (int jc = 16; jc < ncol; ++jc) col_step(std::true_type{}, jc);
   }
   __syncthreads();
 
@@ -572,24 +606,9 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(HeadArgs a) {
   }
   __syncthreads();
 
-  // ---- publish V (clean, scaled), R, T ----
+  // ---- publish V (clean, scaled) and R of the remaining rows, then T ----
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int cl = 16 * h + j;
-    if (cl < ncol) {
-      const int rc = c0 + cl;
-      const double iv = sInv[cl];
-#pragma unroll
-      for (int i = 0; i < NR2; ++i) {
-        const int r = rbase + 16 * i;
-        const double v = h ? x1[i] : x0[i];
-        if (r < d) {
-          a.V[r + (long)rc * d] = (r < rc) ? 0.0 : (r == rc ? 1.0 : v / iv);
-          a.R[r + (long)rc * a.ldr] = (r <= rc) ? v : 0.0;
-        }
-      }
-    }
-  }
+  for (int i = 0; i < NR2; ++i) emit(i, x0[i], x1[i]);
   for (int e = tid; e < PWR * PWR; e += NT) {
     const int i = e % PWR, jj = e / PWR;
     a.T[(long)w * PWR * PWR + e] = (i < ncol && jj < ncol) ? sT[i * LDP + jj] : 0.0;
