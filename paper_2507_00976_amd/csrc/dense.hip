@@ -281,31 +281,30 @@ __global__ __launch_bounds__(256) void trinv_offdiag_kernel(const double* R, lon
       const int e = tid + q * 256;
       xd[q] = X[(pI + e % W32) + (long)(pI + e / W32) * ldx];
     }
-    // S = sum_K R_IK X_KJ; A(i, k) = R(pI + 16 wm + i, pK + k) straight from memory,
-    // next block's operands loaded while the current one is multiplied
+    // S = sum_K R_IK X_KJ; A(i, k) = R(pI + 16 wm + i, pK + k) straight from
+    // memory: the whole block row I (blocks K = I+1 .. J) is requested before
+    // the first product, so a block row costs one memory latency
     const double* arow = R + (pI + 16 * wm + i16);
-    double an[8];
+    double a[NBLK - 1][8];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const int col = (I + 1) * W32 + 4 * s + k4;
-      an[s] = (col < n) ? arow[(long)col * ldr] : 0.0;
+    for (int q = 0; q < NBLK - 1; ++q) {
+      const int K = I + 1 + q;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int col = K * W32 + 4 * s + k4;
+        a[q][s] = (K <= J && col < n) ? arow[(long)col * ldr] : 0.0;
+      }
     }
     dv4 acc = dv4{0.0, 0.0, 0.0, 0.0};
-    for (int K = I + 1; K <= J; ++K) {
-      double a[8];
 #pragma unroll
-      for (int s = 0; s < 8; ++s) a[s] = an[s];
-      if (K < J) {
+    for (int q = 0; q < NBLK - 1; ++q) {
+      const int K = I + 1 + q;
+      if (K <= J) {
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          const int col = (K + 1) * W32 + 4 * s + k4;
-          an[s] = (col < n) ? arow[(long)col * ldr] : 0.0;
-        }
+        for (int s = 0; s < 8; ++s)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q][s], sCol[K][4 * s + k4][16 * wn + i16],
+                                                     acc, 0, 0, 0);
       }
-#pragma unroll
-      for (int s = 0; s < 8; ++s)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], sCol[K][4 * s + k4][16 * wn + i16], acc,
-                                                   0, 0, 0);
     }
     // D(i, j) sits in lane j + 16 (i % 4), register i / 4
 #pragma unroll
@@ -329,6 +328,75 @@ __global__ __launch_bounds__(256) void trinv_offdiag_kernel(const double* R, lon
       if (j < nbJ) X[(pI + i) + (long)(pJ + j) * ldx] = v;
     }
     __syncthreads();
+  }
+}
+
+// The same block-column chain with the finished blocks X_KJ read back from X
+// (written by this workgroup, L2 resident) instead of kept in LDS: 17 KB of
+// LDS, so its workgroups find room on compute units shared with a concurrent
+// GEMM.  Operands are requested CH blocks at a time; the products run in the
+// same order as above (bitwise the same X).
+__global__ __launch_bounds__(256) void trinv_offdiag_gl_kernel(const double* R, long ldr, int n,
+                                                               double* X, long ldx) {
+  constexpr int CH = 3;
+  __shared__ double sS[W32][W32 + 1];
+  __shared__ double sXd[W32][W32 + 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w & 1, wn = w >> 1;
+  const int i16 = lane & 15, k4 = lane >> 4;
+  const int J = blockIdx.x + 1, pJ = J * W32, nbJ = min(W32, n - pJ);
+  const int jcol = 16 * wn + i16;  // this lane's column of X_KJ (B operand)
+  for (int I = J - 1; I >= 0; --I) {
+    const int pI = I * W32;
+    double xd[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * 256;
+      xd[q] = X[(pI + e % W32) + (long)(pI + e / W32) * ldx];
+    }
+    const double* arow = R + (pI + 16 * wm + i16);
+    dv4 acc = dv4{0.0, 0.0, 0.0, 0.0};
+    for (int K0 = I + 1; K0 <= J; K0 += CH) {
+      double a[CH][8], b[CH][8];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int K = K0 + c;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const int kr = K * W32 + 4 * s + k4;  // row of X_KJ / column of R_IK
+          const bool ok = K <= J && kr < n;
+          a[c][s] = ok ? arow[(long)kr * ldr] : 0.0;
+          b[c][s] = (ok && jcol < nbJ) ? X[kr + (long)(pJ + jcol) * ldx] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        if (K0 + c <= J) {
+#pragma unroll
+          for (int s = 0; s < 8; ++s)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][s], b[c][s], acc, 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sS[16 * wm + 4 * r + k4][16 * wn + i16] = acc[r];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * 256;
+      sXd[e % W32][e / W32] = xd[q];
+    }
+    __syncthreads();
+    dv4 acc2 = dv4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+      acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(sXd[16 * wm + i16][4 * s + k4],
+                                                  sS[4 * s + k4][16 * wn + i16], acc2, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * wm + 4 * r + k4, j = 16 * wn + i16;
+      if (j < nbJ) X[(pI + i) + (long)(pJ + j) * ldx] = -acc2[r];
+    }
+    __syncthreads();  // X_IJ visible to the whole workgroup before block row I - 1
   }
 }
 
@@ -362,7 +430,8 @@ __global__ __launch_bounds__(256) void trinv_upper_kernel(const double* R, long 
   }
 }
 
-int launch_trinv_upper(const double* R, i64 ldr, int n, double* X, i64 ldx, hipStream_t st) {
+int launch_trinv_upper(const double* R, i64 ldr, int n, double* X, i64 ldx, hipStream_t st,
+                       bool low_lds) {
   if (n <= 0) return QRCP_OK;
   if (n > 1024) return QRCP_ERR_UNSUPPORTED;
   if (n > 512) {
@@ -376,7 +445,8 @@ int launch_trinv_upper(const double* R, i64 ldr, int n, double* X, i64 ldx, hipS
   QRCP_LAUNCHED("trinv_diag");
   if (nblk > 1) {
     const dim3 g(nblk - 1), b(256);
-    if (nblk <= 8) hipLaunchKernelGGL(trinv_offdiag_kernel<8>, g, b, 0, st, R, ldr, n, X, ldx);
+    if (low_lds) hipLaunchKernelGGL(trinv_offdiag_gl_kernel, g, b, 0, st, R, ldr, n, X, ldx);
+    else if (nblk <= 8) hipLaunchKernelGGL(trinv_offdiag_kernel<8>, g, b, 0, st, R, ldr, n, X, ldx);
     else if (nblk <= 10) hipLaunchKernelGGL(trinv_offdiag_kernel<10>, g, b, 0, st, R, ldr, n, X, ldx);
     else hipLaunchKernelGGL(trinv_offdiag_kernel<16>, g, b, 0, st, R, ldr, n, X, ldx);
     QRCP_LAUNCHED("trinv_offdiag");

@@ -36,7 +36,10 @@ int launch_philox(const uint32_t* ctr, i64 count, uint32_t k0, uint32_t k1, uint
 
 // ---- small dense kernels ----
 // X = R^{-1} for an upper triangular n x n R (X zero below the diagonal).
-int launch_trinv_upper(const double* R, i64 ldr, int n, double* X, i64 ldx, hipStream_t st);
+// low_lds: a variant whose workgroups need little LDS (for launches that run
+// beside a GEMM occupying the compute units).
+int launch_trinv_upper(const double* R, i64 ldr, int n, double* X, i64 ldx, hipStream_t st,
+                       bool low_lds = false);
 // T^{-1} = diag(1/tau) + strictly-upper(G) formed in place in G (n x n), then
 // T = inverse into T (the compact WY factor from Y^T Y and tau).
 int launch_ut_tinv(double* G, i64 ldg, const double* tau, int n, hipStream_t st);

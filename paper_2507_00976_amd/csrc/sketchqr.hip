@@ -378,12 +378,29 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(HeadArgs a) {
       return;
     }
     __threadfence();
-    for (int e = tid; e < DP * PWR; e += NT) {
-      const int rr = e / PWR, aa = e % PWR;
-      sV[rr * LDP + aa] = (aa < pc && rr >= p0 && rr < d) ? a.V[rr + (long)(p0 + aa) * d] : 0.0;
+    {
+      // V_q and T_q: every load requested before the first LDS store (one
+      // memory latency), consecutive threads on consecutive rows of a column
+      constexpr int QV = DP * PWR / NT, QT = PWR * PWR / NT;
+      double vr[QV], tr[QT];
+#pragma unroll
+      for (int q = 0; q < QV; ++q) {
+        const int e = tid + NT * q, rr = e % DP, aa = e / DP;
+        vr[q] = (aa < pc && rr >= p0 && rr < d) ? a.V[rr + (long)(p0 + aa) * d] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < QT; ++q) tr[q] = a.T[(long)p * PWR * PWR + tid + NT * q];
+#pragma unroll
+      for (int q = 0; q < QV; ++q) {
+        const int e = tid + NT * q, rr = e % DP, aa = e / DP;
+        sV[rr * LDP + aa] = vr[q];
+      }
+#pragma unroll
+      for (int q = 0; q < QT; ++q) {
+        const int e = tid + NT * q;
+        sT[(e % PWR) * LDP + e / PWR] = tr[q];  // T(i, j) at i + PWR j
+      }
     }
-    for (int e = tid; e < PWR * PWR; e += NT)
-      sT[(e % PWR) * LDP + e / PWR] = a.T[(long)p * PWR * PWR + e];  // T(i, j) at i + PWR j
     __syncthreads();
     // partial W(aa, c) over my rows: D = A B with A(aa, k) = V(row k, aa), B(k, c) = C(row k, c)
     dv4 acc[2][2];
@@ -694,7 +711,7 @@ int run_sketch_qr(const double* B, int d, i64 ni, i64 ldb, double* R, i64 ldr, v
     g.M = dh; g.N = dh; g.K = d; g.A = V; g.lda = d; g.B = V; g.ldb = d; g.C = G; g.ldc = dh;
     QRCP_TRY(gemm(true, false, Prec::F64, g, split, split_bytes, st));
     QRCP_TRY(launch_ut_tinv(G, dh, tau, dh, st));
-    QRCP_TRY(launch_trinv_upper(G, dh, dh, T, dh, st));
+    QRCP_TRY(launch_trinv_upper(G, dh, dh, T, dh, st, true));  // runs beside the deferred update
     QRCP_TRY(launch_ut_zero_diag(T, dh, tau, dh, st));
     // X = T V^T (dh x d)
     GemmArgs x;
