@@ -278,13 +278,18 @@ __global__ __launch_bounds__(NT) void headlu_mw_kernel(double* Q, long ldq, int 
 #pragma unroll
         for (int c = 0; c < W32; ++c) sBlk[lane][c] = x[c];
       }
-      if (bi + 1 < nb) {
-        double y[W32];
+    }
+    __syncthreads();
+    if (bi + 1 < nb && tid < 128) {
+      // the two triangular inverses side by side: wave 0 U^{-1}, wave 1 L^{-1}
+      double y[W32];
+      if (tid < 64) {
         wave_inv_upper32(&sBlk[0][0], LDB, y, nr);
         if (lane < BS) {
 #pragma unroll
           for (int r = 0; r < W32; ++r) sP[r][lane] = y[r];
         }
+      } else {
         wave_inv_unit_lower32(&sBlk[0][0], LDB, y, nr);
         if (lane < BS) {
 #pragma unroll

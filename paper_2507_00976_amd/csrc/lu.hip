@@ -286,20 +286,45 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
           if (gg < G && !to) {
             uint64_t* r = a.rec + ((long)j * G + gg) * RW;
             uint64_t (&w)[HW] = hdr[qq];
-            long spins = 0;
-            for (;;) {
-              bool miss = false;
+            bool miss = false;
 #pragma unroll
-              for (int i = 0; i < HW; ++i) miss |= (w[i] == SENT);
-              if (!miss) break;
-              if (++spins > kSpinLimit) {
-                to = true;
-                break;
+            for (int i = 0; i < HW; ++i) miss |= (w[i] == SENT);
+            if (miss) {
+              // two polls in flight, started ~500 cycles apart: each check
+              // consumes the older one while the younger travels, so a word
+              // that lands just after one poll is seen by the other (words
+              // never change once written, so the copies merge)
+              uint64_t pa[HW], pb[HW];
+#pragma unroll
+              for (int i = 0; i < HW; ++i) pa[i] = load_agent(r + i);
+              __builtin_amdgcn_s_sleep(8);
+#pragma unroll
+              for (int i = 0; i < HW; ++i) pb[i] = load_agent(r + i);
+              long spins = 0;
+              for (;;) {
+                miss = false;
+#pragma unroll
+                for (int i = 0; i < HW; ++i) {
+                  w[i] = (w[i] == SENT) ? pa[i] : w[i];
+                  miss |= (w[i] == SENT);
+                }
+                if (!miss) break;
+#pragma unroll
+                for (int i = 0; i < HW; ++i) pa[i] = load_agent(r + i);
+                miss = false;
+#pragma unroll
+                for (int i = 0; i < HW; ++i) {
+                  w[i] = (w[i] == SENT) ? pb[i] : w[i];
+                  miss |= (w[i] == SENT);
+                }
+                if (!miss) break;
+#pragma unroll
+                for (int i = 0; i < HW; ++i) pb[i] = load_agent(r + i);
+                if (++spins > kSpinLimit) {
+                  to = true;
+                  break;
+                }
               }
-              __builtin_amdgcn_s_sleep(1);
-#pragma unroll
-              for (int i = 0; i < HW; ++i)
-                if (w[i] == SENT) w[i] = load_agent(r + i);
             }
             if (!to) {
               if (w[1] == BADKEY) {
