@@ -39,6 +39,8 @@ struct HeadArgs {
   double* T;      // npanels x pw x pw
   int* flags;     // npanels, zero on entry
   int* status;
+  double* Tfull;  // may be null: dh x dh T of all panels (ld dh), by the block recursion
+  int* tflags;    // npanels, zero on entry: block column w of Tfull is final
 };
 
 typedef double hv4 __attribute__((ext_vector_type(4)));
@@ -633,6 +635,113 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(HeadArgs a) {
   __threadfence();
   __syncthreads();
   if (tid == 0) store_agent_i32(a.flags + w, 1);
+
+  // ---- block column w of the T of all panels (LARFT block recursion):
+  // T(0:c0, c0:c0+32) = -T(0:c0, 0:c0) (V(:, 0:c0)^T V_w) T_w, T_w on the
+  // diagonal.  Done here, on this workgroup's own compute unit while the next
+  // panel is factored, so the tail needs no Gram product or triangular
+  // inverse.  Columns of earlier panels come from their workgroups (tflags).
+  if (a.Tfull) {
+    const long ldt = dh;
+    const int qi = ws & 1, qj = ws >> 1;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int e = tid; e < PWR * PWR; e += NT) {
+      const int i = e % PWR, jj = e / PWR;
+      if (i < ncol && jj < ncol) a.Tfull[(c0 + i) + (long)(c0 + jj) * ldt] = sT[i * LDP + jj];
+    }
+    // T is upper triangular: zero below the diagonal block
+    const int below = dh - c0 - ncol;
+    for (int e = tid; e < below * ncol; e += NT)
+      a.Tfull[(c0 + ncol + e % below) + (long)(c0 + e / below) * ldt] = 0.0;
+    if (w > 0) {
+      // V_w, rows c0 .. d-1 (zero above), to LDS as [k][j], k = row - c0
+      const int K = d - c0;
+      for (int e = tid; e < K * PWR; e += NT) {
+        const int k = e % K, jj = e / K;
+        sV[k * LDP + jj] = (jj < ncol) ? a.V[(c0 + k) + (long)(c0 + jj) * d] : 0.0;
+      }
+      __syncthreads();
+      for (int I = 0; I < w; ++I) {
+        // Y_I = V_I^T V_w over rows c0 .. d-1: A(i, k) = V(c0 + k, 32 I + i)
+        const double* vcol = a.V + (long)(PWR * I + 16 * qi + li) * d + c0;
+        dv4 acc = dv4{0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < K; k0 += 32) {
+          double av[8];
+#pragma unroll
+          for (int b = 0; b < 8; ++b) {
+            const int k = k0 + 4 * b + lk;
+            av[b] = (k < K) ? vcol[k] : 0.0;
+          }
+#pragma unroll
+          for (int b = 0; b < 8; ++b) {
+            const int k = k0 + 4 * b + lk;
+            const double bv = (k < K) ? sV[k * LDP + 16 * qj + li] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bv, av[b], acc, 0, 0, 0);
+          }
+        }
+        // acc[r] = Y_I(16 qi + li, 16 qj + 4 r + lk)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sW[(16 * qi + li) * LDP + 16 * qj + 4 * r + lk] = acc[r];
+        __syncthreads();
+        // Y'_I = Y_I T_w, parked in T(32 I .., c0 ..) until Z overwrites it
+        dv4 acc2 = dv4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const int k = 4 * s + lk;
+          acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(sT[k * LDP + 16 * qj + li],
+                                                      sW[(16 * qi + li) * LDP + k], acc2, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int jj = 16 * qj + 4 * r + lk;
+          if (jj < ncol) a.Tfull[(PWR * I + 16 * qi + li) + (long)(c0 + jj) * ldt] = acc2[r];
+        }
+        __syncthreads();
+      }
+      // columns 0 .. c0 of T, published by the earlier workgroups
+      if (tid == 0) {
+        for (int q = 0; q < w && !sbad; ++q) {
+          long spins = 0;
+          while (load_agent_i32(a.tflags + q) == 0) {
+            if (++spins > kSpinLimit) { sbad = 1; break; }
+            __builtin_amdgcn_s_sleep(2);
+          }
+        }
+      }
+      __syncthreads();
+      if (sbad) {
+        if (tid == 0) store_agent_i32(a.status, QRCP_ERR_TIMEOUT);
+        return;
+      }
+      __threadfence();
+      // Z_I = -sum_{J=I}^{w-1} T(I, J) Y'_J for I = 0 .. w-1, written over Y'_I
+      for (int I = 0; I < w; ++I) {
+        dv4 acc = dv4{0.0, 0.0, 0.0, 0.0};
+        for (int J = I; J < w; ++J) {
+          double av[8], bv[8];
+#pragma unroll
+          for (int s = 0; s < 8; ++s) {
+            const int k = 4 * s + lk;
+            av[s] = a.Tfull[(PWR * I + 16 * qi + li) + (long)(PWR * J + k) * ldt];
+            const int jj = 16 * qj + li;
+            bv[s] = (jj < ncol) ? a.Tfull[(PWR * J + k) + (long)(c0 + jj) * ldt] : 0.0;
+          }
+#pragma unroll
+          for (int s = 0; s < 8; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[s], av[s], acc, 0, 0, 0);
+        }
+        __syncthreads();  // every wave has read Y'_I
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int jj = 16 * qj + 4 * r + lk;
+          if (jj < ncol) a.Tfull[(PWR * I + 16 * qi + li) + (long)(c0 + jj) * ldt] = -acc[r];
+        }
+        __syncthreads();
+      }
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) store_agent_i32(a.tflags + w, 1);
+  }
 }
 
 }  // namespace
@@ -657,7 +766,7 @@ size_t sketch_qr_ws_bytes(int d, i64 ni) {
   b += (size_t)dh * dh * 8;         // T full
   b += (size_t)dh * d * 8;          // X = T V^T
   b += (size_t)d * d * 8;           // Q
-  b += (size_t)np * 4 + 256;        // flags
+  b += (size_t)(np + 1) * 8 + 256;  // panel flags, T column flags
   b += gemm_splitk_bytes(dh, dh, 64);
   return b + 8 * 64;
 }
@@ -679,12 +788,14 @@ int run_sketch_qr(const double* B, int d, i64 ni, i64 ldb, double* R, i64 ldr, v
   double* T = (double*)take((size_t)dh * dh * 8);
   double* X = (double*)take((size_t)dh * d * 8);
   double* Q = (double*)take((size_t)d * d * 8);
-  int* flags = (int*)take((size_t)(np + 1) / 2 * 8);
+  int* flags = (int*)take((size_t)(np + 1) * 8);  // panel flags, then the T column flags
   double* split = (double*)take(gemm_splitk_bytes(dh, dh, 64));
   const size_t split_bytes = gemm_splitk_bytes(dh, dh, 64);
 
-  QRCP_TRY(launch_fill_u64((uint64_t*)flags, (np + 1) / 2, 0ull, st));
-  HeadArgs args{B, (long)ldb, d, dh, pw, R, (long)ldr, V, tau, Tp, flags, status_dev};
+  QRCP_TRY(launch_fill_u64((uint64_t*)flags, np + 1, 0ull, st));
+  const bool tfull = d <= 320;  // the register head builds T of all panels
+  HeadArgs args{B, (long)ldb, d, dh, pw, R, (long)ldr, V, tau, Tp, flags, status_dev,
+                tfull ? T : nullptr, flags + np};
   void* params[] = {&args};
   if (d <= 320) {
     const int nr2 = d <= 128 ? 8 : (d <= 192 ? 12 : 20);
@@ -706,13 +817,15 @@ int run_sketch_qr(const double* B, int d, i64 ni, i64 ldb, double* R, i64 ldr, v
   }
 
   if (ni > dh) {
-    // T = (diag(1/tau) + striu(V^T V))^{-1}
-    GemmArgs g;
-    g.M = dh; g.N = dh; g.K = d; g.A = V; g.lda = d; g.B = V; g.ldb = d; g.C = G; g.ldc = dh;
-    QRCP_TRY(gemm(true, false, Prec::F64, g, split, split_bytes, st));
-    QRCP_TRY(launch_ut_tinv(G, dh, tau, dh, st));
-    QRCP_TRY(launch_trinv_upper(G, dh, dh, T, dh, st, true));  // runs beside the deferred update
-    QRCP_TRY(launch_ut_zero_diag(T, dh, tau, dh, st));
+    if (!tfull) {
+      // T = (diag(1/tau) + striu(V^T V))^{-1}
+      GemmArgs g;
+      g.M = dh; g.N = dh; g.K = d; g.A = V; g.lda = d; g.B = V; g.ldb = d; g.C = G; g.ldc = dh;
+      QRCP_TRY(gemm(true, false, Prec::F64, g, split, split_bytes, st));
+      QRCP_TRY(launch_ut_tinv(G, dh, tau, dh, st));
+      QRCP_TRY(launch_trinv_upper(G, dh, dh, T, dh, st, true));  // runs beside the deferred update
+      QRCP_TRY(launch_ut_zero_diag(T, dh, tau, dh, st));
+    }
     // X = T V^T (dh x d)
     GemmArgs x;
     x.M = dh; x.N = d; x.K = dh; x.A = T; x.lda = dh; x.B = V; x.ldb = d; x.C = X; x.ldc = dh;
