@@ -272,14 +272,19 @@ def run_serving(args, torch, qrcp, WD):
     dev = torch.device("cuda:0")
     rng = np.random.default_rng(args.seed)
     nreq = args.requests
-    shapes = []
-    for i in range(nreq):
+    # the stream draws from a pool of distinct matrices (request i factors
+    # matrix i % pool, restored from a pristine copy; a buffer is refilled only
+    # after its previous request has finished)
+    pool = min(nreq, 1000)
+    pshapes = []
+    for i in range(pool):
         m = int(np.exp(rng.uniform(np.log(256), np.log(4096))))
         n = int(np.exp(rng.uniform(np.log(64), np.log(min(m, 1024)))))
-        shapes.append((m, n, i % 3))
+        pshapes.append((m, n, i % 3))
+    shapes = [pshapes[i % pool] for i in range(nreq)]
     t0 = time.perf_counter()
     mats = []
-    for i, (m, n, kind) in enumerate(shapes):
+    for i, (m, n, kind) in enumerate(pshapes):
         if kind == 0:
             sig = WD.geometric_spectrum(n, 1e-10)
         else:
@@ -288,15 +293,16 @@ def run_serving(args, torch, qrcp, WD):
                 sig[n // 2:] = 0.0
         mats.append(WD.usv(m, n, sig, args.seed + 1 + i, dev))
     torch.cuda.synchronize()
-    log(f"generated {nreq} requests in {time.perf_counter() - t0:.1f}s")
+    log(f"generated {pool} matrices for {nreq} requests in {time.perf_counter() - t0:.1f}s")
     pristine = [x.clone() for x in mats]
     flops = [canonical_flops(m, n) for m, n, _ in shapes]
 
     def submit_all(srv, order_times=None):
-        tickets, arrive = [], []
+        tickets = []
         tstart = time.perf_counter()
         done = {}
-        pending = []
+        pending = set()
+        owner = [None] * pool      # the ticket that last used each buffer
         for i, (m, n, kind) in enumerate(shapes):
             if order_times is not None:
                 while time.perf_counter() - tstart < order_times[i]:
@@ -304,15 +310,20 @@ def run_serving(args, torch, qrcp, WD):
                         r = srv.poll(t)
                         if r is not None:
                             done[t] = r
-                            pending.remove(t)
+                            pending.discard(t)
                     time.sleep(0.0002)
-            mats[i].copy_(pristine[i])
+            j = i % pool
+            if owner[j] is not None and owner[j] in pending:
+                done[owner[j]] = srv.wait(owner[j])
+                pending.discard(owner[j])
+            mats[j].copy_(pristine[j])
             b = min(64, n)
             tol = 1e-13 if kind == 2 else 0.0
-            t = srv.submit(mats[i], b, 1.25, 42, tol)
+            t = srv.submit(mats[j], b, 1.25, 42, tol)
+            owner[j] = t
             tickets.append(t)
-            pending.append(t)
-        for t in pending:
+            pending.add(t)
+        for t in list(pending):
             done[t] = srv.wait(t)
         wall = time.perf_counter() - tstart
         res = [done[t] for t in tickets]
@@ -323,11 +334,17 @@ def run_serving(args, torch, qrcp, WD):
         cap = nreq / wall
         log(f"closed loop: {nreq} requests in {wall:.2f}s = {cap:.1f} req/s, "
             f"{sum(flops) / wall / 1e9:.1f} GFLOP/s")
-        lam = args.load * cap
-        gaps = rng.exponential(1.0 / lam, nreq)
-        times = np.cumsum(gaps) - gaps[0]
-        wall, res = submit_all(srv, times)
-    lat = np.array([r[4]["end_ms"] - r[4]["submit_ms"] for r in res])
+        open_loop = {}
+        for load in (args.load, 0.5):
+            lam_l = load * cap
+            gaps = rng.exponential(1.0 / lam_l, nreq)
+            times = np.cumsum(gaps) - gaps[0]
+            wall_l, res_l = submit_all(srv, times)
+            lat_l = np.array([r[4]["end_ms"] - r[4]["submit_ms"] for r in res_l])
+            open_loop[load] = (lam_l, wall_l, res_l, lat_l)
+            log(f"open loop at {lam_l:.1f} req/s offered ({load}x): {nreq / wall_l:.1f} req/s, "
+                f"p50 {np.percentile(lat_l, 50):.3f} ms, p99 {np.percentile(lat_l, 99):.3f} ms")
+        lam, wall, res, lat = open_loop[args.load]
     ranks_ok = all(r[3] == (shapes[i][1] // 2 if shapes[i][2] == 2 else shapes[i][1])
                    for i, r in enumerate(res))
     out = {"metric": "QRCP serving req/s + p99 latency", "value": round(nreq / wall, 2),
@@ -337,10 +354,16 @@ def run_serving(args, torch, qrcp, WD):
            "mean_ms": round(float(lat.mean()), 3),
            "closed_loop_req_s": round(cap, 2), "offered_req_s": round(lam, 2),
            "aggregate_gflops": round(sum(flops) / wall / 1e9, 1), "ranks_as_expected": ranks_ok,
+           "open_loop": {f"{ld}x": {"offered_req_s": round(v[0], 2),
+                                    "req_s": round(nreq / v[1], 2),
+                                    "p50_ms": round(float(np.percentile(v[3], 50)), 3),
+                                    "p99_ms": round(float(np.percentile(v[3], 99)), 3)}
+                         for ld, v in open_loop.items()},
            "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"{nreq} requests, m in [256,4096], n in [64,min(m,1024)] "
-                                  f"log-uniform, b=min(64,n), d=ceil(1.25b), Poisson arrivals at "
-                                  f"{args.load}x closed-loop capacity", "slots": args.slots}}
+           "config": {"workload": f"{nreq} requests over {pool} distinct matrices, m in [256,4096], "
+                                  f"n in [64,min(m,1024)] log-uniform, b=min(64,n), d=ceil(1.25b), "
+                                  f"Poisson arrivals at {args.load}x (and 0.5x) closed-loop capacity",
+                      "slots": args.slots}}
     log(f"open loop at {lam:.1f} req/s offered: {nreq / wall:.1f} req/s, p50 {out['p50_ms']} ms, "
         f"p99 {out['p99_ms']} ms")
     print(json.dumps(out), flush=True)
@@ -364,7 +387,7 @@ def main():
                     help="headline: 16384^2 (default); precision: 65536x8192 FP64 / BF16-sketch / "
                          "FP32-trailing variants; lowrank: 32768^2 rank-4096 detection; serving: "
                          "Poisson stream of mixed-shape requests through the request server")
-    ap.add_argument("--requests", type=int, default=1000, help="serving: number of requests")
+    ap.add_argument("--requests", type=int, default=10000, help="serving: number of requests")
     ap.add_argument("--slots", type=int, default=4, help="serving: concurrent requests")
     ap.add_argument("--load", type=float, default=0.8,
                     help="serving: offered rate as a fraction of the closed-loop capacity")

@@ -367,40 +367,38 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(HeadArgs a) {
   for (int p = 0; p < w; ++p) {
     const int p0 = p * PWR;
     const int pc = min(PWR, dh - p0);
-    if (tid == 0) {
-      long spins = 0;
-      while (load_agent_i32(a.flags + p) == 0) {
-        if (++spins > kSpinLimit) { sbad = 1; break; }
-        __builtin_amdgcn_s_sleep(2);
+    // panel flag: 1 = V_p published, 2 = T_p published as well
+    auto wait_flag = [&](int v) -> bool {
+      if (tid == 0) {
+        long spins = 0;
+        while (load_agent_i32(a.flags + p) < v) {
+          if (++spins > kSpinLimit) { sbad = 1; break; }
+          __builtin_amdgcn_s_sleep(2);
+        }
       }
-    }
-    __syncthreads();
-    if (sbad) {
-      if (tid == 0) store_agent_i32(a.status, QRCP_ERR_TIMEOUT);
-      return;
-    }
-    __threadfence();
+      __syncthreads();
+      if (sbad) {
+        if (tid == 0) store_agent_i32(a.status, QRCP_ERR_TIMEOUT);
+        return false;
+      }
+      __threadfence();
+      return true;
+    };
+    if (!wait_flag(1)) return;
     {
-      // V_q and T_q: every load requested before the first LDS store (one
-      // memory latency), consecutive threads on consecutive rows of a column
-      constexpr int QV = DP * PWR / NT, QT = PWR * PWR / NT;
-      double vr[QV], tr[QT];
+      // V_p: every load requested before the first LDS store (one memory
+      // latency), consecutive threads on consecutive rows of a column
+      constexpr int QV = DP * PWR / NT;
+      double vr[QV];
 #pragma unroll
       for (int q = 0; q < QV; ++q) {
         const int e = tid + NT * q, rr = e % DP, aa = e / DP;
         vr[q] = (aa < pc && rr >= p0 && rr < d) ? a.V[rr + (long)(p0 + aa) * d] : 0.0;
       }
 #pragma unroll
-      for (int q = 0; q < QT; ++q) tr[q] = a.T[(long)p * PWR * PWR + tid + NT * q];
-#pragma unroll
       for (int q = 0; q < QV; ++q) {
         const int e = tid + NT * q, rr = e % DP, aa = e / DP;
         sV[rr * LDP + aa] = vr[q];
-      }
-#pragma unroll
-      for (int q = 0; q < QT; ++q) {
-        const int e = tid + NT * q;
-        sT[(e % PWR) * LDP + e / PWR] = tr[q];  // T(i, j) at i + PWR j
       }
     }
     __syncthreads();
@@ -433,6 +431,19 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(HeadArgs a) {
       const int e = tid + NT * q, aa = e / PWR, c = e % PWR;
       sW[aa * LDP + c] = (sWp[aa * LDP + c] + sWp[(PWR + aa) * LDP + c]) +
                          (sWp[(2 * PWR + aa) * LDP + c] + sWp[(3 * PWR + aa) * LDP + c]);
+    }
+    // T_p (published after V_p, while this workgroup formed W)
+    if (!wait_flag(2)) return;
+    {
+      constexpr int QT = PWR * PWR / NT;
+      double tr[QT];
+#pragma unroll
+      for (int q = 0; q < QT; ++q) tr[q] = a.T[(long)p * PWR * PWR + tid + NT * q];
+#pragma unroll
+      for (int q = 0; q < QT; ++q) {
+        const int e = tid + NT * q;
+        sT[(e % PWR) * LDP + e / PWR] = tr[q];  // T(i, j) at i + PWR j
+      }
     }
     __syncthreads();
     // W' = T^T W: wave ws computes block (ws & 1, ws >> 1)
@@ -596,6 +607,14 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(HeadArgs a) {
   }
   __syncthreads();
 
+  // ---- publish V (clean, scaled) and R of the remaining rows: the next
+  // workgroups start forming V^T C while T is computed ----
+#pragma unroll
+  for (int i = 0; i < NR2; ++i) emit(i, x0[i], x1[i]);
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) store_agent_i32(a.flags + w, 1);
+
   // ---- T of the panel: invert diag(1/tau) + striu(G) (a zero tau decouples
   // its index: its row and column of T are zero) ----
   if (tid < 64) {
@@ -625,16 +644,13 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(HeadArgs a) {
   }
   __syncthreads();
 
-  // ---- publish V (clean, scaled) and R of the remaining rows, then T ----
-#pragma unroll
-  for (int i = 0; i < NR2; ++i) emit(i, x0[i], x1[i]);
   for (int e = tid; e < PWR * PWR; e += NT) {
     const int i = e % PWR, jj = e / PWR;
     a.T[(long)w * PWR * PWR + e] = (i < ncol && jj < ncol) ? sT[i * LDP + jj] : 0.0;
   }
   __threadfence();
   __syncthreads();
-  if (tid == 0) store_agent_i32(a.flags + w, 1);
+  if (tid == 0) store_agent_i32(a.flags + w, 2);
 
   // ---- block column w of the T of all panels (LARFT block recursion):
   // T(0:c0, c0:c0+32) = -T(0:c0, 0:c0) (V(:, 0:c0)^T V_w) T_w, T_w on the
