@@ -7,13 +7,17 @@
 // rows each, with a working copy of the rows in HBM.
 //
 // Pivot steps run panel by panel (32 columns).  During the steps of a panel
-// only wave 0 of each workgroup works: lane l holds the panel part of rows
+// wave 0 of each workgroup runs the steps: lane l holds the panel part of rows
 // l, l+64, ... in registers, shifted left by one column after each step so
-// that the current column is always register 0.  The other three waves join
-// for the blocked trailing update after the panel:
+// that the current column is always register 0.  The blocked trailing update
 //   U12 = L11^{-1} X(piv, trail),  X(r, trail) -= L(r, panel) U12
 // (forward substitution in registers, then the product on the FP64 matrix
-// cores).
+// cores) is split in two: right after the panel all four waves update the
+// next panel's 32 columns, and the remaining columns are updated by waves 1-3
+// while wave 0 already runs the next panel's steps (panel state in LDS is
+// double-buffered for this).  A workgroup publishes its last header of a panel
+// only after that background update is in memory, so a workgroup that has
+// read every header of the panel may read any pivot row's trailing values.
 //
 // One pivot step costs one cross-workgroup round trip.  Every workgroup
 // publishes a record for its best candidate: a header (|x|, key = current
@@ -50,6 +54,8 @@ constexpr uint64_t NOCAND = 0x7FFFFFFF00000000ull;
 constexpr uint64_t BADKEY = 0x7FFFFFFE00000000ull;
 constexpr int kMaxGroups = 256;
 constexpr int GQ = kMaxGroups / 64;  // records read per lane
+constexpr int LRBG = 2;  // row blocks per request group of the update beside the steps
+constexpr int LUB = 8;   // pivot-row loads per request group of that update
 
 typedef double dv4 __attribute__((ext_vector_type(4)));
 
@@ -121,18 +127,90 @@ __device__ __forceinline__ uint64_t canon(double x) {
 
 __device__ __forceinline__ double cand_value(double x) { return isnan(x) ? -0.5 : fabs(x); }
 
+// X(r, col) -= L(r, panel) U12(panel, col) for the row blocks rb0 .. rb0+NRBX
+// of a workgroup (16 x 16 blocks on the FP64 matrix cores; D(i, j) sits in
+// lane j + 16 (i % 4)).  `col` is this lane's matrix column, `uc` its column
+// of the U12 staging array; rows that are no longer active are left alone.
+// Row blocks go RBG at a time, each group's loads and stores completed before
+// the next group's are issued: the update that runs beside the pivot steps
+// keeps few requests in the compute unit's memory queue, where the steps'
+// record loads would wait behind them.
+template <int NRBX, int RBG, int LS, int US>
+__device__ __forceinline__ void lu_tile_update(double* xw, long row0, int d, int col, int rb0,
+                                               const double (*L)[LS], const double (*U)[US],
+                                               int uc, const int* act, int i16, int k4) {
+  static_assert(NRBX % RBG == 0, "row-block groups");
+#pragma unroll
+  for (int g0 = 0; g0 < NRBX; g0 += RBG) {
+    double old[RBG][4];
+#pragma unroll
+    for (int rb = 0; rb < RBG; ++rb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int lr = (rb0 + g0 + rb) * 16 + 4 * r + k4;
+        old[rb][r] = (act[lr] && col < d) ? xw[(row0 + lr) * d + col] : 0.0;
+      }
+#pragma unroll
+    for (int rb = 0; rb < RBG; ++rb) {
+      dv4 acc = dv4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < NB / 4; ++s)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(L[(rb0 + g0 + rb) * 16 + i16][4 * s + k4],
+                                                   U[4 * s + k4][uc], acc, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int lr = (rb0 + g0 + rb) * 16 + 4 * r + k4;
+        if (act[lr] && col < d) xw[(row0 + lr) * d + col] = old[rb][r] - acc[r];
+      }
+    }
+    if (RBG < NRBX) {
+      __builtin_amdgcn_s_waitcnt(0);  // this group's requests retired
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+// u := L11^{-1} u for the unit lower triangular L11 of a panel (rows 16-byte
+// aligned in LDS, read two multipliers at a time by every lane at once).  Row
+// t + 1 is requested before row t is applied, so each LDS round trip overlaps
+// a row of arithmetic instead of a single multiply-add.
+__device__ __forceinline__ void lu_forward_subst(double (&u)[NB], const double (*L)[NB + 2]) {
+  double2 cur[NB / 2], nxt[NB / 2];
+  nxt[0] = reinterpret_cast<const double2*>(L[1])[0];
+#pragma unroll
+  for (int t = 1; t < NB; ++t) {
+#pragma unroll
+    for (int s2 = 0; 2 * s2 < t; ++s2) cur[s2] = nxt[s2];
+    if (t + 1 < NB) {
+#pragma unroll
+      for (int s2 = 0; 2 * s2 < t + 1; ++s2)
+        nxt[s2] = reinterpret_cast<const double2*>(L[t + 1])[s2];
+    }
+    double acc = u[t];
+#pragma unroll
+    for (int s2 = 0; 2 * s2 < t; ++s2) {
+      acc -= cur[s2].x * u[2 * s2];
+      if (2 * s2 + 1 < t) acc -= cur[s2].y * u[2 * s2 + 1];
+    }
+    u[t] = acc;
+  }
+}
+
 template <int RPT>
 __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
   constexpr int R = 64 * RPT;
   // row strides padded so that the matrix-core operand reads are free of bank conflicts
-  __shared__ double sU[NB][TCH + 16];    // U12 chunk
-  __shared__ double sLr[R][NB + 2];      // multipliers of this workgroup's rows
-  __shared__ double sL11[NB][NB + 1];    // multipliers of the panel's pivot rows
-  __shared__ long sRow[NB];              // the panel's pivot rows
+  // Panel state is double-buffered by panel parity: waves 1-3 update the
+  // trailing columns with panel p's multipliers while wave 0 runs the steps
+  // of panel p + 1.
+  __shared__ double sU[NB][TCH + 16];    // U12 chunk (trail_b: one slice per wave)
+  __shared__ double sLr[2][R][NB + 2];   // multipliers of this workgroup's rows
+  __shared__ __align__(16) double sL11[2][NB][NB + 2];  // multipliers of the panel's pivot rows
+  __shared__ long sRow[2][NB];           // the panel's pivot rows
   __shared__ double sPs[64];             // previous pivot row, shifted to the current column
   __shared__ double sCand[NB];           // panel row of the published candidate
-  __shared__ int sAct[R];
-  __shared__ int sBad, sErr;
+  __shared__ int sAct[2][R];
+  __shared__ int sBad, sErr, sTrailCnt;
 
   const int g = blockIdx.x, G = gridDim.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -146,6 +224,7 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
   if (tid == 0) {
     sBad = 0;
     sErr = 0;
+    sTrailCnt = 0;
   }
   __syncthreads();
   {
@@ -174,8 +253,10 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
     pos[q] = act[q] ? row[q] : LONG_MAX;
   }
 
-  for (int p0 = 0; p0 < steps; p0 += NB) {
+  constexpr int NRB = R / 16;
+  for (int p0 = 0, pi = 0; p0 < steps; p0 += NB, ++pi) {
     const int ns = min(NB, steps - p0);
+    const int par = pi & 1;
     if (wv == 0) {
       double x[RPT][NB];
 #pragma unroll
@@ -191,6 +272,21 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
       uint64_t pay = 0;        // payload word `lane` of the previous winner (in flight)
       uint64_t* prev_rec = a.rec;
       bool to = false;
+      // The trailing update of the previous panel (waves 1-3) must be in
+      // memory before this workgroup's last header of the panel: whoever
+      // reads that header reads the updated rows afterwards.
+      auto wait_trail = [&]() {
+        if (pi == 0) return;
+        long spins = 0;
+        while (__hip_atomic_load(&sTrailCnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) <
+               3 * pi) {
+          if (++spins > kSpinLimit) {
+            to = true;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      };
 
       // Publishes the candidate of step j (column 0 of x; column 1 gives the
       // next-column value): the five header words go out in one store
@@ -252,11 +348,12 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
         }
         wave_lds_sync();
         if (lane < NB) {
-          const double v = (lane < jl) ? sLr[olr][lane] : sCand[lane - jl];
+          const double v = (lane < jl) ? sLr[par][olr][lane] : sCand[lane - jl];
           store_agent(a.rec + ((long)j * G + g) * RW + HW + lane, canon(v));
         }
       };
 
+      if (ns == 1) wait_trail();
       publish_payload(p0, publish_header(p0, lprev));
       for (int jl = 0; jl < ns; ++jl) {
         const int j = p0 + jl;
@@ -385,7 +482,7 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
             break;
           }
           const double raw = bitsd(pay);
-          if (lane < jl - 1) sL11[jl - 1][lane] = raw;
+          if (lane < jl - 1) sL11[par][jl - 1][lane] = raw;
           pcur = (lane >= jl && lane < NB) ? raw - lam_prev * pprev : 0.0;
         }
         // broadcast copy: sPs[t] = pivot row j-1 in panel column jl+1+t (0 past the panel)
@@ -396,7 +493,7 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
         pay = (lane < NB) ? load_agent(wrec + HW + lane) : 0;
         prev_rec = wrec;
         if (lane == 0) {
-          sRow[jl] = wrow;
+          sRow[par][jl] = wrow;
           if (g == 0) {
             a.ipiv[j] = wpos;
             a.jsk[j] = wrow;
@@ -415,7 +512,7 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
           x[q][1] = (x[q][1] - lprev[q] * s1) - l * pj1;
           x[q][2] -= lprev[q] * s2;
           lnew[q] = l;
-          sLr[lane + 64 * q][jl] = l;
+          sLr[par][lane + 64 * q][jl] = l;
         }
         // shift: column j+1 becomes register 0
 #pragma unroll
@@ -424,6 +521,7 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
           for (int t = 0; t < NB - 1; ++t) x[q][t] = x[q][t + 1];
           x[q][NB - 1] = 0.0;
         }
+        if (jl + 2 == ns) wait_trail();
         const int olr = (jl + 1 < ns) ? publish_header(j + 1, lnew) : -1;
         // previous pivot's contribution to the remaining panel columns
 #pragma unroll
@@ -458,65 +556,94 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
             sErr = 1;
           }
         } else if (lane < ns - 1) {
-          sL11[ns - 1][lane] = bitsd(pay);
+          sL11[par][ns - 1][lane] = bitsd(pay);
         }
       }
 #pragma unroll
-      for (int q = 0; q < RPT; ++q) sAct[lane + 64 * q] = act[q] ? 1 : 0;
+      for (int q = 0; q < RPT; ++q) sAct[par][lane + 64 * q] = act[q] ? 1 : 0;
+    } else if (pi > 0) {
+      // ---- previous panel's update of columns p0 + NB .. d (waves 1-3) ----
+      // Each wave takes 64-column groups with its own slice of sU, so the
+      // three waves never wait for each other, and none waits for wave 0.
+      const int pb = par ^ 1, uc0 = 64 * (wv - 1);
+      for (int c0 = p0 + NB + uc0; c0 < d; c0 += 192) {
+        const int cw = min(64, d - c0);
+        if (lane < cw) {
+          double u[NB];
+#pragma unroll
+          for (int t0 = 0; t0 < NB; t0 += LUB) {
+#pragma unroll
+            for (int t = t0; t < t0 + LUB; ++t) u[t] = a.xw[sRow[pb][t] * (long)d + c0 + lane];
+            __builtin_amdgcn_s_waitcnt(0);
+            __builtin_amdgcn_sched_barrier(0);
+          }
+          lu_forward_subst(u, sL11[pb]);
+#pragma unroll
+          for (int t = 0; t < NB; ++t) sU[t][uc0 + lane] = u[t];
+        }
+        wave_lds_sync();
+        const int ncb = (cw + 15) / 16;
+        for (int cb = 0; cb < ncb; ++cb)
+          lu_tile_update<NRB, LRBG>(a.xw, row0, d, c0 + cb * 16 + i16, 0, sLr[pb], sU,
+                              uc0 + cb * 16 + i16, sAct[pb], i16, k4);
+        wave_lds_sync();
+      }
+      __threadfence();  // release: the updated rows before wave 0's last header
+      if (lane == 0)
+        __hip_atomic_fetch_add(&sTrailCnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     __syncthreads();
     if (sErr) return;  // uniform
     const int pend = p0 + ns;
     if (pend >= steps) break;  // no later pivot step needs the trailing columns
 
-    // ---- blocked trailing update of columns pend .. d ----
-    __threadfence();  // acquire: pivot rows' trailing values written by their owners
-    for (int c0 = pend; c0 < d; c0 += TCH) {
-      const int cw = min(TCH, d - c0);
+    // ---- this panel's update of the next panel's columns (all waves) ----
+    // The rest of the trailing columns is updated by waves 1-3 during the
+    // next panel's pivot steps.
+    // acquire: pivot rows' trailing values written by their owners
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    {
+      constexpr int HRB = NRB / 2;
+      const int cw = min(NB, d - pend);
+      const int cb = wv & 1, rb0 = (wv >> 1) * HRB;
+      const int col = pend + cb * 16 + i16;
+      // this wave's block of own rows, requested before the substitution
+      double old[HRB][4];
+#pragma unroll
+      for (int rb = 0; rb < HRB; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int lr = (rb0 + rb) * 16 + 4 * r + k4;
+          old[rb][r] = (sAct[par][lr] && col < pend + cw) ? a.xw[(row0 + lr) * d + col] : 0.0;
+        }
       if (tid < cw) {
         double u[NB];
 #pragma unroll
-        for (int t = 0; t < NB; ++t) u[t] = a.xw[sRow[t] * (long)d + c0 + tid];
-#pragma unroll
-        for (int t = 1; t < NB; ++t)
-#pragma unroll
-          for (int s = 0; s < t; ++s) u[t] -= sL11[t][s] * u[s];
+        for (int t = 0; t < NB; ++t) u[t] = a.xw[sRow[par][t] * (long)d + pend + tid];
+        lu_forward_subst(u, sL11[par]);
 #pragma unroll
         for (int t = 0; t < NB; ++t) sU[t][tid] = u[t];
       }
       __syncthreads();
-      // X(r, chunk) -= L(r, panel) U12: 16 x 16 blocks, D(i, j) in lane j + 16 (i % 4)
-      constexpr int NRB = R / 16;
-      const int ncb = (cw + 15) / 16;
-      for (int cb = wv; cb < ncb; cb += 4) {
-        const int col = c0 + cb * 16 + i16;
-        double old[NRB][4];
+      if (cb * 16 < cw) {
 #pragma unroll
-        for (int rb = 0; rb < NRB; ++rb)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int lr = rb * 16 + 4 * r + k4;
-            old[rb][r] = (sAct[lr] && col < d) ? a.xw[(row0 + lr) * d + col] : 0.0;
-          }
-#pragma unroll
-        for (int rb = 0; rb < NRB; ++rb) {
+        for (int rb = 0; rb < HRB; ++rb) {
           dv4 acc = dv4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int s = 0; s < 8; ++s)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sLr[rb * 16 + i16][4 * s + k4],
-                                                       sU[4 * s + k4][cb * 16 + i16], acc, 0, 0,
-                                                       0);
+          for (int s = 0; s < NB / 4; ++s)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sLr[par][(rb0 + rb) * 16 + i16][4 * s + k4],
+                                                       sU[4 * s + k4][cb * 16 + i16], acc, 0, 0, 0);
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int lr = rb * 16 + 4 * r + k4;
-            if (sAct[lr] && col < d) a.xw[(row0 + lr) * d + col] = old[rb][r] - acc[r];
+            const int lr = (rb0 + rb) * 16 + 4 * r + k4;
+            if (sAct[par][lr] && col < pend + cw) a.xw[(row0 + lr) * d + col] = old[rb][r] - acc[r];
           }
         }
       }
-      __syncthreads();
     }
-    __threadfence();  // release: my trailing values before the next records
-    __syncthreads();
+    // Only this workgroup's wave 0 reads these columns (its next panel); the
+    // rows other workgroups read were released by waves 1-3.
+    __syncthreads();  // the next panel's columns before wave 0 loads them
   }
   // positions of the rows that were never pivots
   if (wv == 0) {

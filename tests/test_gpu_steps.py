@@ -64,7 +64,8 @@ def test_sketch_gemm_bf16(Q):
 
 
 # ---- a3: LU pivots -------------------------------------------------------------
-@pytest.mark.parametrize("d,ni", [(80, 512), (80, 37), (320, 1000), (33, 5000), (64, 64), (320, 16384)])
+@pytest.mark.parametrize("d,ni", [(80, 512), (80, 37), (320, 1000), (33, 5000), (64, 64), (97, 3000),
+                                  (700, 4096), (320, 16384)])
 def test_lu_pivots_match_oracle(Q, d, ni):
     msk = W.gaussian(d, ni, seed=d * ni)
     ipiv_ref, margins = O.getrf_pivots(msk.T)
