@@ -5,10 +5,12 @@
 //   row layout:    lane r holds row r,    x[c] = M(r, c).
 // Lanes 32..63 carry zeros and their results are ignored.  Every loop index is
 // a compile-time constant after unrolling; the rows or columns that every lane
-// needs are broadcast through a small LDS buffer of the calling wave (written
-// and read by the same wave, so no barrier is involved), and the updates are
-// written without per-element branches: entries outside the triangle that a
-// caller uses may hold garbage, which never flows into the triangle.
+// needs at a factorization step are broadcast through a small LDS buffer of
+// the calling wave (written and read by the same wave, so no barrier is
+// involved) or read from their lane as scalars, the inverses request the next row of the triangle while applying
+// the current one, and the updates are written without per-element branches:
+// entries outside the triangle that a caller uses may hold garbage, which
+// never flows into the triangle.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -27,8 +29,43 @@ __device__ __forceinline__ double rdlane(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// Newton-Raphson refinements of the hardware approximations (each step
+// roughly doubles the number of correct bits; two steps from the hardware
+// estimate reach double precision up to a unit or two in the last place).
+// Arguments outside [2^-1000, 2^1000] take the exact library operations, so
+// neither the estimate nor its square can leave the normal range.
+__device__ __forceinline__ bool nr_range(double a) {
+  const double m = fabs(a);
+  return m >= 0x1p-1000 && m <= 0x1p1000;
+}
+// 1 / sqrt(d) for d > 0
+__device__ __forceinline__ double nr_rsqrt(double d) {
+  if (!nr_range(d)) return 1.0 / sqrt(d);
+  double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-d * y, y, 1.0);  // 1 - d y^2
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+// 1 / a for a != 0
+__device__ __forceinline__ double nr_rcp(double a) {
+  if (!nr_range(a)) return 1.0 / a;
+  double y = __builtin_amdgcn_rcp(a);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-a, y, 1.0);  // 1 - a y
+    y = fma(y, e, y);
+  }
+  return y;
+}
+
 // Cholesky of the upper triangle, column layout, in place: on return
 // x[r] = R(r, c) for r <= c (the entries below the diagonal are garbage).
+// With y = 1/sqrt(pivot) (refined hardware estimate), row t is x(t, c) y off
+// the diagonal and pivot * y on it: a handful of dependent operations per step
+// instead of a square root followed by a division.
 // Returns the first column t whose pivot is not positive (breakdown), else
 // nb; from the breakdown on, columns are left as they were at that point.
 // sb: 64 doubles of LDS owned by the calling wave.
@@ -39,8 +76,9 @@ __device__ __forceinline__ int wave_potrf32_col(double (&x)[W32], int nb, double
     if (t < nb) {
       const double d = rdlane(x[t], t);
       if (!(d > 0.0)) return t;
-      const double r = sqrt(d);
-      const double q = x[t] / r;
+      const double y = nr_rsqrt(d);
+      const double r = d * y;
+      const double q = x[t] * y;
       x[t] = (lane == t) ? r : ((lane > t) ? q : x[t]);
       sb[lane] = x[t];  // row t of R: R(t, c) in lane c
       wave_lds_sync();
@@ -56,22 +94,34 @@ __device__ __forceinline__ int wave_potrf32_col(double (&x)[W32], int nb, double
 // y = R^{-1} (column layout) for the upper triangle of R held in LDS,
 // row-major with stride ld (only entries on and above the diagonal are
 // read): back substitution R X = I, one column of X per lane, four partial
-// sums per dot product.
+// sums per dot product.  The reciprocals of the diagonal are formed first, all
+// lanes at once, so each row costs a multiplication instead of a division.
 __device__ __forceinline__ void wave_inv_upper32(const double* sR, int ld, double (&y)[W32],
                                                  int nb) {
   const int lane = threadIdx.x & 63;
   wave_lds_sync();
+  const double dinv = (lane < nb) ? 1.0 / sR[lane * ld + lane] : 0.0;  // lane i: 1 / R(i, i)
+  // row i - 1 of R is requested while row i is applied
+  double cur[W32], nxt[W32];
+  nxt[W32 - 1] = sR[(W32 - 2) * ld + W32 - 1];
 #pragma unroll
   for (int i = 0; i < W32; ++i) y[i] = 0.0;
 #pragma unroll
   for (int i = W32 - 1; i >= 0; --i) {
-    if (i < nb) {
-      double s[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int l = i + 1; l < W32; ++l) s[l & 3] = fma(sR[i * ld + l], y[l], s[l & 3]);
-      const double rii = sR[i * ld + i];
-      const double sum = (s[0] + s[1]) + (s[2] + s[3]);
-      y[i] = (lane == i) ? 1.0 / rii : ((lane > i && lane < nb) ? -sum / rii : 0.0);
+    for (int l = i + 1; l < W32; ++l) cur[l] = nxt[l];
+    if (i >= 1) {
+#pragma unroll
+      for (int l = i; l < W32; ++l) nxt[l] = sR[(i - 1) * ld + l];
+    }
+    if (i < nb) {
+      double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int l = i + 1; l < W32; ++l) s4[l & 3] = fma(cur[l], y[l], s4[l & 3]);
+      const double di = rdlane(dinv, i);
+      const double v = -((s4[0] + s4[1]) + (s4[2] + s4[3])) * di;
+      const double keep = (lane > i && lane < nb) ? v : 0.0;
+      y[i] = (lane == i) ? di : keep;
     }
   }
 }
@@ -83,14 +133,24 @@ __device__ __forceinline__ void wave_inv_unit_lower32(const double* sL, int ld, 
                                                       int nb) {
   const int lane = threadIdx.x & 63;
   wave_lds_sync();
+  // row i + 1 of L is requested while row i is applied
+  double cur[W32], nxt[W32];
+  nxt[0] = sL[1 * ld + 0];
 #pragma unroll
   for (int i = 0; i < W32; ++i) {
-    if (i < nb) {
-      double s[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int l = 0; l < i; ++l) s[l & 3] = fma(sL[i * ld + l], y[l], s[l & 3]);
-      const double sum = (s[0] + s[1]) + (s[2] + s[3]);
-      y[i] = (lane == i) ? 1.0 : ((lane < i) ? -sum : 0.0);
+    for (int l = 0; l < i; ++l) cur[l] = nxt[l];
+    if (i + 1 < W32) {
+#pragma unroll
+      for (int l = 0; l <= i; ++l) nxt[l] = sL[(i + 1) * ld + l];
+    }
+    if (i < nb) {
+      double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int l = 0; l < i; ++l) s4[l & 3] = fma(cur[l], y[l], s4[l & 3]);
+      const double v = -((s4[0] + s4[1]) + (s4[2] + s4[3]));
+      const double keep = (lane < i) ? v : 0.0;
+      y[i] = (lane == i) ? 1.0 : keep;
     } else {
       y[i] = 0.0;
     }
@@ -100,10 +160,11 @@ __device__ __forceinline__ void wave_inv_unit_lower32(const double* sL, int ld, 
 // LU without pivoting with the sign modification of the Householder
 // reconstruction (row layout, in place): at step t, D_t = -sgn(M(t,t))
 // (sgn(0) = +1), the pivot becomes M(t,t) - D_t, the column below it is
-// divided by the pivot and the trailing block updated.  Lane 0 stores D_t to
-// dj[t].  sb: 64 doubles of LDS owned by the calling wave.
+// scaled by the pivot's (refined) reciprocal and the trailing block updated.  Lane 0 stores D_t to
+// dj[t].  sb is not used.
 __device__ __forceinline__ void wave_lu32_signmod_row(double (&x)[W32], int nb, double* dj,
                                                       double* sb) {
+  (void)sb;
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int t = 0; t < W32; ++t) {
@@ -112,18 +173,13 @@ __device__ __forceinline__ void wave_lu32_signmod_row(double (&x)[W32], int nb, 
       const double d = (a >= 0.0) ? -1.0 : 1.0;
       const double piv = a - d;
       if (lane == 0) dj[t] = d;
-      const double q = x[t] / piv;
+      const double q = x[t] * nr_rcp(piv);
       x[t] = (lane == t) ? piv : ((lane > t) ? q : x[t]);
-      // row t of U, from lane t, to every lane
-      if (lane == t) {
-#pragma unroll
-        for (int c = t + 1; c < W32; ++c) sb[c] = x[c];
-      }
-      wave_lds_sync();
+      // row t of U is lane t's registers, read as scalars (one lane would
+      // otherwise write it to LDS element by element)
       const double l = (lane > t) ? x[t] : 0.0;  // rows at and above t keep their values
 #pragma unroll
-      for (int c = t + 1; c < W32; ++c) x[c] = fma(-l, sb[c], x[c]);
-      wave_lds_sync();
+      for (int c = t + 1; c < W32; ++c) x[c] = fma(-l, rdlane(x[c], t), x[c]);
     }
   }
 }
