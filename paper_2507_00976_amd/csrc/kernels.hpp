@@ -78,9 +78,12 @@ int launch_scale_cols_lower_copy(double* dst, i64 ldd, const double* src, i64 ld
 int launch_any_nonfinite(const double* X, i64 ld, i64 rows, i64 cols, int* flag, hipStream_t st);
 
 // ---- pivot selection (cooperative GETRF pivots) ----
-size_t lu_records_bytes(int d, i64 ni);
+// max_steps > 0 stops the elimination after that many steps (ipiv[0:steps] and
+// the positions they imply); 0 runs all min(d, ni) steps.
+size_t lu_records_bytes(int d, i64 ni, int max_steps = 0);
 int launch_lu_pivots(const double* Msk, int d, i64 ni, i64 ld, double* Xw, uint64_t* rec,
-                     size_t rec_bytes, i64* ipiv, i64* jsk, int* status_dev, hipStream_t st);
+                     size_t rec_bytes, i64* ipiv, i64* jsk, int* status_dev, hipStream_t st,
+                     int max_steps = 0);
 
 // ---- sketch QR (cooperative head + explicit Q^T for the tail) ----
 size_t sketch_qr_ws_bytes(int d, i64 ni);

@@ -64,6 +64,7 @@ struct LuArgs {
   long ld;
   int d;
   long ni;
+  int steps;         // elimination steps: at most min(d, ni)
   double* xw;        // ni x d row-major working copy
   uint64_t* rec;     // steps x G x RW words, sentinel-filled
   long* ipiv;
@@ -217,7 +218,7 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
   const int i16 = lane & 15, k4 = lane >> 4;
   const int d = a.d;
   const long ni = a.ni;
-  const int steps = (int)min((long)d, ni);
+  const int steps = a.steps;
   const long row0 = (long)g * R;
 
   // working copy of this workgroup's rows + non-finite check
@@ -672,24 +673,28 @@ int lu_resident_groups(i64 ni) {
   return rpt ? (int)((ni + 64L * rpt - 1) / (64L * rpt)) : 0;
 }
 
-size_t lu_records_bytes(int d, i64 ni) {
+size_t lu_records_bytes(int d, i64 ni, int max_steps) {
   const int rpt = pick_rpt(ni);
   if (!rpt) return 0;
   const long G = (ni + 64L * rpt - 1) / (64L * rpt);
-  const long steps = std::min((long)d, (long)ni);
+  long steps = std::min((long)d, (long)ni);
+  if (max_steps > 0) steps = std::min(steps, (long)max_steps);
   return (size_t)steps * G * RW * sizeof(uint64_t);
 }
 
 int launch_lu_pivots(const double* Msk, int d, i64 ni, i64 ld, double* Xw, uint64_t* rec,
-                     size_t rec_bytes, i64* ipiv, i64* jsk, int* status_dev, hipStream_t st) {
+                     size_t rec_bytes, i64* ipiv, i64* jsk, int* status_dev, hipStream_t st,
+                     int max_steps) {
   if (ni <= 0 || d <= 0) return QRCP_OK;
   const int rpt = pick_rpt(ni);
   if (!rpt) return QRCP_ERR_UNSUPPORTED;
-  const size_t need = lu_records_bytes(d, ni);
+  const size_t need = lu_records_bytes(d, ni, max_steps);
   if (need > rec_bytes) return QRCP_ERR_WORKSPACE;
   const int G = (int)((ni + 64L * rpt - 1) / (64L * rpt));
+  int steps = (int)std::min((long)d, (long)ni);
+  if (max_steps > 0) steps = std::min(steps, max_steps);
   QRCP_TRY(launch_fill_u64(rec, (i64)(need / sizeof(uint64_t)), SENT, st));
-  LuArgs args{Msk, (long)ld, d, (long)ni, Xw, rec, (long*)ipiv, (long*)jsk, status_dev};
+  LuArgs args{Msk, (long)ld, d, (long)ni, steps, Xw, rec, (long*)ipiv, (long*)jsk, status_dev};
   void* params[] = {&args};
   const void* fn = rpt == 1 ? (const void*)lu_pivots_kernel<1> : (const void*)lu_pivots_kernel<2>;
   QRCP_TRY(launch_resident(fn, dim3(G), dim3(NT), params, 0, st));

@@ -415,16 +415,23 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
   int cur = 0;
   i64 ell = 0;
   int status = QRCP_OK;
+  // QRCP_LU_ALLSTEPS=1 runs every elimination step of the pivot selection (the
+  // full GETRF of the sketch); the selected columns and factors are the same
+  const bool lu_all_steps = getenv("QRCP_LU_ALLSTEPS") != nullptr;
   for (i64 s = 0; s < n; ) {
     const i64 ni = n - s, mi = m - s;
     const int kmax = (int)std::min<i64>(b, std::min(ni, mi));
     const i64 c = s + kmax;
     double* Ablk = A + s + s * lda;  // panel top-left (rows s.., physical column s)
-    // 1. pivots of the sketch (Alg. 2 GETRF on the transpose)
+    // 1. pivots of the sketch (Alg. 2 GETRF on the transpose).  Only the first
+    // kmax elimination steps run: partial pivoting at step j depends on the
+    // steps before j alone, so they fix the kmax selected columns, and the
+    // later steps would only reorder the columns this block leaves, which the
+    // next block selects among again.
     {
-      ProfScope ps(kStLu, 2.0 * ni * d * d, st);
+      ProfScope ps(kStLu, 2.0 * ni * d * kmax, st);
       QRCP_TRY(launch_lu_pivots(w.sk0 + s * d, d, ni, d, w.xw, w.rec, w.rec_bytes, w.ipiv, w.jsk,
-                                w.status, st));
+                                w.status, st, lu_all_steps ? 0 : kmax));
     }
     // 2. logical maps and the placement plan; 3. permuted sketch
     {

@@ -144,3 +144,32 @@ def test_lowrank_rank_detection_repeatable(Q, b):
         assert np.array_equal(got.jpiv, runs[0].jpiv)
         assert np.array_equal(got.tau, runs[0].tau)
         assert np.array_equal(got.a, runs[0].a)
+
+
+@pytest.mark.parametrize("m,n,b,gamma,tol", [(1500, 1200, 128, 1.25, 0.0), (700, 650, 64, 2.0, 0.0),
+                                             (400, 171, 32, 1.25, 0.0), (2048, 2048, 256, 1.25, 0.0),
+                                             (900, 900, 64, 1.25, 1e-9)])
+def test_pivot_steps_limited_to_block(Q, monkeypatch, m, n, b, gamma, tol):
+    """The pivot selection stops after the block's k elimination steps instead
+    of the full GETRF of the sketch: partial pivoting at step j depends only on
+    the steps before j, and the columns left behind are selected among again by
+    the next block, so the pivots are those of the full GETRF and the factors
+    agree to rounding (the trailing columns are processed in another order)."""
+    sig = 1.0 / (np.arange(n) + 1.0) ** 2
+    if tol > 0:
+        sig[n // 2:] = 0.0
+    a = W.usv(m, n, sig, seed=m + 3 * n)
+    monkeypatch.setenv("QRCP_LU_ALLSTEPS", "1")
+    full = run_gpu(Q, a, b, gamma, 5, tol)
+    monkeypatch.delenv("QRCP_LU_ALLSTEPS")
+    part = run_gpu(Q, a, b, gamma, 5, tol)
+    assert part.rank == full.rank
+    r = full.rank
+    assert np.array_equal(part.jpiv[:r], full.jpiv[:r])
+    if r == min(m, n):
+        assert np.array_equal(part.jpiv, full.jpiv)
+        nrm = np.linalg.norm(a)
+        assert np.max(np.abs(np.triu(part.a) - np.triu(full.a))) <= R_TOL * nrm
+        np.testing.assert_allclose(part.tau, full.tau, rtol=1e-9, atol=1e-12)
+    resid, orth = O.residual_and_orth(a, part)
+    assert resid <= R_TOL and orth <= R_TOL
