@@ -116,7 +116,8 @@ int qrcp_philox(const uint32_t* ctr, int64_t count, uint32_t key0, uint32_t key1
                 void* stream);
 /* M^sk = S A (Alg. 1 sketching step).  A DEVICE m x n (lda), Msk DEVICE d x n
  * (ldmsk >= d).  precision: 0 FP64, 1 BF16 operands with FP32 accumulation.
- * workspace >= m*d doubles (holds S^T). */
+ * workspace >= m*d*8 + 40 MiB + 512 bytes (S^T, then split-K partials of
+ * the product); less gives QRCP_ERR_WORKSPACE. */
 int qrcp_sketch(const double* A, int64_t m, int64_t n, int64_t lda, int64_t d, uint64_t seed,
                 int32_t precision, double* Msk, int64_t ldmsk, void* workspace,
                 size_t workspace_bytes, void* stream);

@@ -408,11 +408,14 @@ static void launch_shape(const GemmArgs& g, int splits, hipStream_t st) {
 
 size_t gemm_splitk_bytes(long M, long N, int splits) { return (size_t)M * N * splits * sizeof(double); }
 
-// Chooses a split of K when the output has too few tiles to fill the GPU.
-int gemm_pick_splits(long M, long N, long K) {
+// Chooses a split of K when the output has too few tiles to fill the GPU:
+// about `target` workgroups (512 by default; the W = Y^T C product of the
+// trailing update, whose tiles each run the whole long K, asks for 1024,
+// four per compute unit).
+int gemm_pick_splits(long M, long N, long K, long target) {
   const long tiles = ((M + 63) / 64) * ((N + 63) / 64);
-  if (tiles >= 256 || K < 512) return 1;
-  long s = (512 + tiles - 1) / tiles;
+  if (2 * tiles >= target || K < 512) return 1;
+  long s = (target + tiles - 1) / tiles;
   const long kmax = K / 256;  // keep >= 256 per split
   if (s > kmax) s = kmax;
   if (s > 64) s = 64;
@@ -431,8 +434,10 @@ int gemm(bool ta, bool tb, Prec prec, GemmArgs g, double* split_ws, size_t split
     return QRCP_OK;
   }
   int splits = 1;
-  if (split_ws && !g.bcol) splits = gemm_pick_splits(g.M, g.N, g.K);
-  if (splits > 1 && gemm_splitk_bytes(g.M, g.N, splits) > split_ws_bytes) splits = 1;
+  if (split_ws && !g.bcol)
+    splits = gemm_pick_splits(g.M, g.N, g.K, g.kind == GemmKind::TrailingW ? 1024 : 512);
+  if (splits > 1 && gemm_splitk_bytes(g.M, g.N, splits) > split_ws_bytes)
+    splits = (int)std::max<size_t>(1, split_ws_bytes / gemm_splitk_bytes(g.M, g.N, 1));
   const long BKc = 32;
   long chunk = (g.K + splits - 1) / splits;
   chunk = (chunk + BKc - 1) / BKc * BKc;

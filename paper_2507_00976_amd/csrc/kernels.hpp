@@ -27,7 +27,7 @@ struct GemmArgs {
 int gemm(bool ta, bool tb, Prec prec, GemmArgs g, double* split_ws, size_t split_ws_bytes,
          hipStream_t st);
 size_t gemm_splitk_bytes(long M, long N, int splits);
-int gemm_pick_splits(long M, long N, long K);
+int gemm_pick_splits(long M, long N, long K, long target = 512);
 
 // ---- sketch operator ----
 int launch_sketch_operator(double* St, i64 m, int d, i64 ldst, uint64_t seed, hipStream_t st);

@@ -116,7 +116,7 @@ struct ProfScope {
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr size_t kSplitBytes = 40u << 20;  // split-K partials (any shape fits, see gemm_pick_splits)
+constexpr size_t kSplitBytes = 52u << 20;  // split-K partials (any shape fits, see gemm_pick_splits)
 
 struct Carver {
   char* base;
@@ -677,15 +677,16 @@ int qrcp_sketch(const double* A, int64_t m, int64_t n, int64_t lda, int64_t d, u
   if (d < 1) return -5;
   if (precision != 0 && precision != 1) return -7;
   if (ldmsk < d) return -9;
-  const size_t need = (size_t)m * d * 8 + kSplitBytes + 2 * kAlign;
+  constexpr size_t kSketchSplitBytes = 40u << 20;  // the sketch product's split-K partials
+  const size_t need = (size_t)m * d * 8 + kSketchSplitBytes + 2 * kAlign;
   if (!workspace || workspace_bytes < need) return QRCP_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
   Carver c{(char*)workspace};
   double* St = c.take<double>((size_t)m * d);
-  double* split = c.take<double>(kSplitBytes / 8);
+  double* split = c.take<double>(kSketchSplitBytes / 8);
   QRCP_TRY(launch_sketch_operator(St, m, (int)d, m, seed, st));
   QRCP_TRY(gemm(true, false, precision ? Prec::BF16 : Prec::F64,
-                ga((int)d, (int)n, (int)m, St, m, A, lda, Msk, ldmsk), split, kSplitBytes, st));
+                ga((int)d, (int)n, (int)m, St, m, A, lda, Msk, ldmsk), split, kSketchSplitBytes, st));
   QRCP_HIP(hipStreamSynchronize(st));
   return QRCP_OK;
 }
