@@ -410,8 +410,8 @@ size_t gemm_splitk_bytes(long M, long N, int splits) { return (size_t)M * N * sp
 
 // Chooses a split of K when the output has too few tiles to fill the GPU:
 // about `target` workgroups (512 by default; the W = Y^T C product of the
-// trailing update, whose tiles each run the whole long K, asks for 1024,
-// four per compute unit).
+// trailing update, whose tiles each run the whole long K, asks for 4096, so
+// that every product below 2048 tiles is split, within the partials area).
 int gemm_pick_splits(long M, long N, long K, long target) {
   const long tiles = ((M + 63) / 64) * ((N + 63) / 64);
   if (2 * tiles >= target || K < 512) return 1;
@@ -435,7 +435,7 @@ int gemm(bool ta, bool tb, Prec prec, GemmArgs g, double* split_ws, size_t split
   }
   int splits = 1;
   if (split_ws && !g.bcol)
-    splits = gemm_pick_splits(g.M, g.N, g.K, g.kind == GemmKind::TrailingW ? 1024 : 512);
+    splits = gemm_pick_splits(g.M, g.N, g.K, g.kind == GemmKind::TrailingW ? 4096 : 512);
   if (splits > 1 && gemm_splitk_bytes(g.M, g.N, splits) > split_ws_bytes)
     splits = (int)std::max<size_t>(1, split_ws_bytes / gemm_splitk_bytes(g.M, g.N, 1));
   const long BKc = 32;

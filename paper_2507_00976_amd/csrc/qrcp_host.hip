@@ -116,7 +116,7 @@ struct ProfScope {
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr size_t kSplitBytes = 52u << 20;  // split-K partials (any shape fits, see gemm_pick_splits)
+constexpr size_t kSplitBytes = 112u << 20;  // split-K partials (any shape fits, see gemm_pick_splits)
 
 struct Carver {
   char* base;
