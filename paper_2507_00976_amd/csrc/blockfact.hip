@@ -114,8 +114,7 @@ __global__ __launch_bounds__(NT) void potrf_mw_kernel(double* G, long ldg, int n
   __shared__ double sBlk[BS][LDB];
   __shared__ double sP[BS][LDB];
   __shared__ double sQ[BS][LDB];
-  __shared__ double sBc[64];
-  __shared__ int sres, sbrk;
+  __shared__ int sres, sbrk, sflag;
   int bi = 0, bj = 0;
   {
     int idx = blockIdx.x;
@@ -135,7 +134,10 @@ __global__ __launch_bounds__(NT) void potrf_mw_kernel(double* G, long ldg, int n
     const int r = e % BS, c = e / BS;
     sBlk[r][c] = (r < nr && c < nc && (bi != bj || r <= c)) ? G[(r0 + r) + (long)(c0 + c) * ldg] : 0.0;
   }
-  if (tid == 0) sbrk = -1;
+  if (tid == 0) {
+    sbrk = -1;
+    sflag = 0;
+  }
   __syncthreads();
   bool stop = false;
   // trailing updates of steps p < bi: G_ij -= R_pi^T R_pj
@@ -156,25 +158,20 @@ __global__ __launch_bounds__(NT) void potrf_mw_kernel(double* G, long ldg, int n
     __syncthreads();
   }
   if (!stop && bi == bj) {
+    // wave 0 factors (rows of R published to sQ), wave 1 builds the inverse
+    // into sP row by row behind it
     if (tid < 64) {
       double x[W32];
 #pragma unroll
       for (int r = 0; r < W32; ++r) x[r] = (lane < BS) ? sBlk[r][lane] : 0.0;
-      const int t = wave_potrf32_col(x, nr, sBc);
+      const int t = wave_potrf32_col_pub(x, nr, &sQ[0][0], LDB, &sflag);
       if (lane < BS) {
 #pragma unroll
         for (int r = 0; r < W32; ++r) sBlk[r][lane] = (r <= lane) ? x[r] : 0.0;
       }
-      if (t < nr) {
-        if (lane == 0) sbrk = t;
-      } else if (bi + 1 < nb) {
-        double y[W32];
-        wave_inv_upper32(&sBlk[0][0], LDB, y, nr);
-        if (lane < BS) {
-#pragma unroll
-          for (int r = 0; r < W32; ++r) sP[r][lane] = y[r];
-        }
-      }
+      if (t < nr && lane == 0) sbrk = t;
+    } else if (tid < 128 && bi + 1 < nb) {
+      wave_inv_upper32_follow(&sQ[0][0], LDB, &sP[0][0], LDB, nr, &sflag);
     }
     __syncthreads();
     if (sbrk >= 0) {

@@ -467,8 +467,7 @@ __global__ __launch_bounds__(256) void potrf_upper_kernel(double* G, long ldg, i
   __shared__ double sX[SB][SB + 1];
   __shared__ double sA[SB][TTP];
   __shared__ double sB[SB][TTP];
-  __shared__ double sBc[64];
-  __shared__ int brk;
+  __shared__ int brk, sflag;
   const int tid = threadIdx.x, lane = tid & 63;
   if (tid == 0) brk = -1;
   for (int p0 = 0; p0 < n; p0 += SB) {
@@ -478,26 +477,22 @@ __global__ __launch_bounds__(256) void potrf_upper_kernel(double* G, long ldg, i
       const int tr = e % SB, tc = e / SB;
       sD[tr][tc] = (tr < nb && tc < nb && tr <= tc) ? G[(p0 + tr) + (long)(p0 + tc) * ldg] : 0.0;
     }
+    if (tid == 0) sflag = 0;
     __syncthreads();
+    // wave 0 factors (rows of R published to sA), wave 1 builds the inverse
+    // into sX row by row behind it
     if (tid < 64) {
       double x[W32];
 #pragma unroll
       for (int r = 0; r < W32; ++r) x[r] = (lane < SB) ? sD[r][lane] : 0.0;
-      const int t = wave_potrf32_col(x, nb, sBc);
+      const int t = wave_potrf32_col_pub(x, nb, &sA[0][0], TTP, &sflag);
       if (lane < SB) {
 #pragma unroll
         for (int r = 0; r < W32; ++r) sD[r][lane] = (r <= lane) ? x[r] : 0.0;
       }
-      if (t < nb) {
-        if (lane == 0) brk = p0 + t;
-      } else if (rest > 0) {
-        double y[W32];
-        wave_inv_upper32(&sD[0][0], SB + 1, y, nb);
-        if (lane < SB) {
-#pragma unroll
-          for (int r = 0; r < W32; ++r) sX[r][lane] = y[r];
-        }
-      }
+      if (t < nb && lane == 0) brk = p0 + t;
+    } else if (tid < 128 && rest > 0) {
+      wave_inv_upper32_follow(&sA[0][0], TTP, &sX[0][0], SB + 1, nb, &sflag);
     }
     __syncthreads();
     for (int e = tid; e < SB * SB; e += blockDim.x) {

@@ -91,6 +91,78 @@ __device__ __forceinline__ int wave_potrf32_col(double (&x)[W32], int nb, double
   return nb;
 }
 
+// Cholesky as wave_potrf32_col, for wave 0 of a workgroup whose wave 1 builds
+// the inverse meanwhile (wave_inv_upper32_follow): each finished row t of R
+// (R(t, c), c >= t, at sRows[t * ldr + c]; ldr >= 33) is published with
+// *flag = t + 1 (LDS, release) before it is applied; a breakdown publishes -1.
+// *flag must be 0 when both waves start.
+__device__ __forceinline__ int wave_potrf32_col_pub(double (&x)[W32], int nb, double* sRows,
+                                                    int ldr, int* flag) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int t = 0; t < W32; ++t) {
+    if (t < nb) {
+      const double d = rdlane(x[t], t);
+      if (!(d > 0.0)) {
+        if (lane == 0) __hip_atomic_store(flag, -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        return t;
+      }
+      const double y = nr_rsqrt(d);
+      const double r = d * y;
+      const double q = x[t] * y;
+      x[t] = (lane == t) ? r : ((lane > t) ? q : x[t]);
+      if (lane < W32) sRows[t * ldr + lane] = x[t];
+      wave_lds_sync();
+      if (lane == 0) __hip_atomic_store(flag, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      // G(rr, c) -= R(t, rr) R(t, c) for t < rr <= c
+#pragma unroll
+      for (int rr = t + 1; rr < W32; ++rr) x[rr] = fma(-sRows[t * ldr + rr], x[t], x[rr]);
+    }
+  }
+  return nb;
+}
+
+// R^{-1} for the R that wave_potrf32_col_pub is producing, built as the forward
+// substitution of R^T: as soon as row t of R is published, row t of R^{-T}
+// follows (lane j: R^{-1}(j, t) = -(sum_{s<t} R(s, t) R^{-1}(j, s)) / R(t, t),
+// 1 / R(t, t) on the diagonal, 0 for j > t).  Lane j ends with row j of R^{-1},
+// stored to sInv[j * ldi + t] (zero outside nb x nb).  Returns false, storing
+// nothing, when the factorization breaks down.
+__device__ __forceinline__ bool wave_inv_upper32_follow(const double* sRows, int ldr, double* sInv,
+                                                        int ldi, int nb, int* flag) {
+  const int lane = threadIdx.x & 63;
+  double z[W32];
+#pragma unroll
+  for (int t = 0; t < W32; ++t) z[t] = 0.0;
+#pragma unroll
+  for (int t = 0; t < W32; ++t) {
+    if (t < nb) {
+      long spins = 0;
+      int f = __hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      while (f >= 0 && f <= t) {
+        if (++spins > kSpinLimit) {
+          f = -1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        f = __hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+      if (f < 0) return false;
+      double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < t; ++s) s4[s & 3] = fma(sRows[s * ldr + t], z[s], s4[s & 3]);
+      const double dinv = 1.0 / sRows[t * ldr + t];
+      const double v = -((s4[0] + s4[1]) + (s4[2] + s4[3])) * dinv;
+      z[t] = (lane == t) ? dinv : ((lane < t) ? v : 0.0);
+    }
+  }
+  if (lane < W32) {
+#pragma unroll
+    for (int t = 0; t < W32; ++t) sInv[lane * ldi + t] = z[t];
+  }
+  return true;
+}
+
 // y = R^{-1} (column layout) for the upper triangle of R held in LDS,
 // row-major with stride ld (only entries on and above the diagonal are
 // read): back substitution R X = I, one column of X per lane, four partial
