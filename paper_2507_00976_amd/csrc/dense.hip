@@ -635,6 +635,26 @@ int launch_write_r11(const double* P, i64 ldp, int k, const double* dsig, double
 // ---------------------------------------------------------------------------
 // Copies and fills (2D, column-major).  One thread per element, rows fastest.
 // ---------------------------------------------------------------------------
+// X = triu(S) diag(dvec) (n x n, column-major): the upper triangle of S with
+// column j scaled by dvec(j), zeros below the diagonal.
+__global__ void scale_upper_cols_kernel(const double* S, long lds, const double* dvec, int n,
+                                        double* X, long ldx) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= (long)n * n) return;
+  const long i = e % n, j = e / n;
+  X[i + j * ldx] = (i <= j) ? S[i + j * lds] * dvec[j] : 0.0;
+}
+
+int launch_scale_upper_cols(const double* S, i64 lds, const double* dvec, int n, double* X,
+                            i64 ldx, hipStream_t st) {
+  if (n <= 0) return QRCP_OK;
+  const long total = (long)n * n;
+  hipLaunchKernelGGL(scale_upper_cols_kernel, dim3((total + 255) / 256), dim3(256), 0, st, S,
+                     (long)lds, dvec, n, X, (long)ldx);
+  QRCP_LAUNCHED("scale_upper_cols");
+  return QRCP_OK;
+}
+
 __global__ void copy2d_kernel(const double* src, long lds, double* dst, long ldd, long rows,
                               long cols, int mode) {
   const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;

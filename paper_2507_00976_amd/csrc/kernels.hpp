@@ -67,6 +67,9 @@ int launch_tau_from_u(const double* Q, i64 ldq, int k, const double* dsig, doubl
 int launch_write_r11(const double* P, i64 ldp, int k, const double* dsig, double* A, i64 lda,
                      hipStream_t st);
 // generic helpers
+// X = triu(S) diag(dvec), n x n
+int launch_scale_upper_cols(const double* S, i64 lds, const double* dvec, int n, double* X,
+                            i64 ldx, hipStream_t st);
 int launch_copy2d(const double* src, i64 lds, double* dst, i64 ldd, i64 rows, i64 cols,
                   hipStream_t st);
 int launch_fill(double* dst, i64 ld, i64 rows, i64 cols, double v, hipStream_t st);

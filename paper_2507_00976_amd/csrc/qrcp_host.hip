@@ -535,8 +535,14 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
     QRCP_TRY(apply_qt_rows(w.Y, 0, k, k, m, Ct, nc, lda, tprec, w.W2, st));
     // 12. sketch update: M^sk(0:b, c:) = Rsk12 - Rsk11 R11^{-1} R12 (R12 read through the map)
     ProfScope psu(kStSketchUpdate, 2.0 * b * b * (n - c), st);
-    QRCP_TRY(launch_trinv_upper(Ablk, lda, (int)b, w.R11inv, b, st));
-    QRCP_TRY(gemm(false, false, Prec::F64, ga((int)b, (int)b, (int)b, Rsk, d, w.R11inv, b, w.X, b), nullptr, 0, st));
+    if (o.cholqr_passes == 1) {
+      // R11 = diag(D) Rc Rsk11, so Rsk11 R11^{-1} = Rc^{-1} diag(D): the
+      // inverse of the Cholesky factor is at hand (Q = M^pre Rc^{-1})
+      QRCP_TRY(launch_scale_upper_cols(w.Rinv, b, w.dsig, (int)b, w.X, b, st));
+    } else {
+      QRCP_TRY(launch_trinv_upper(Ablk, lda, (int)b, w.R11inv, b, st));
+      QRCP_TRY(gemm(false, false, Prec::F64, ga((int)b, (int)b, (int)b, Rsk, d, w.R11inv, b, w.X, b), nullptr, 0, st));
+    }
     {
       GemmArgs g = ga((int)b, (int)(n - c), (int)b, w.X, b, A + s, lda, w.sk0 + c * d, d, -1.0, 1.0);
       g.bcol = w.phys[cur] + c;
