@@ -50,6 +50,14 @@ typedef struct qrcp_opts {
   int32_t trailing_precision; /* 0 = FP64 trailing update (default);
                                  1 = FP32 operands and accumulation, FP64 storage    */
   int32_t pivot_base;         /* 0 (default) or 1: base of the returned jpiv         */
+  int32_t pivot_steps;        /* 0 = the full GETRF of each block's sketch, min(d, n_i)
+                                 elimination steps (Alg. 2, default);
+                                 1 = only the block's k_max = min(b, n_i, m_i) steps:
+                                 the same selected columns (partial pivoting at step j
+                                 depends on the steps before j alone), but the columns
+                                 that no block selects (the residual block after an
+                                 early exit) come out in another order, and R agrees
+                                 with the default only to rounding                      */
 } qrcp_opts;
 
 /* Bytes of DEVICE workspace qrcp_factor needs for these sizes and options. */
@@ -68,7 +76,9 @@ size_t qrcp_workspace_size(int64_t m, int64_t n, int64_t block_size, double sket
  *  m, n    m >= n >= 0 (m < n returns QRCP_ERR_UNSUPPORTED).
  *  block_size   b >= 1.
  *  sketch_factor gamma >= 1; the sketch has d = ceil(gamma*b) rows
- *          (d <= 1024 and n <= 65536, else QRCP_ERR_UNSUPPORTED).
+ *          (d <= 1024 and n <= 32768, else QRCP_ERR_UNSUPPORTED, returned
+ *          before any launch: the pivot selection keeps the n_i x d
+ *          transposed sketch in at most 256 resident workgroups of 128 rows).
  *  seed    key of the Philox4x32-10 stream that draws the Gaussian sketching
  *          operator (Sec. 2: randomness is used once, before the loop).
  *  tol     >= 0; block rank = leading run of |Rsk(t,t)| > tol * (largest
@@ -172,6 +182,14 @@ int qrcp_apply_qt(const double* Y, int64_t mi, int64_t k, int64_t ldy, const dou
 int qrcp_sketch_update(double* Rsk, int64_t d, int64_t b, int64_t nt, int64_t ldrsk,
                        const double* R11, int64_t ldr11, const double* R12, int64_t ldr12,
                        void* workspace, size_t workspace_bytes, void* stream);
+/* The same update as qrcp_factor forms it after one Cholesky QR pass
+ * (Alg. 3 with R11 = diag(D) Rc Rsk11): Rsk11 R11^{-1} = Rc^{-1} diag(D), so
+ *   Out(0:b, :) = Rsk12 - Rc^{-1} diag(D) R12.
+ * Rc DEVICE b x b upper (ldrc), dsig DEVICE b (entries +-1), the rest as in
+ * qrcp_sketch_update; workspace >= 2 b^2 doubles + 1 KiB. */
+int qrcp_sketch_update_chol(double* Rsk, int64_t d, int64_t b, int64_t nt, int64_t ldrsk,
+                            const double* Rc, int64_t ldrc, const double* dsig, const double* R12,
+                            int64_t ldr12, void* workspace, size_t workspace_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Request server: many independent factorizations of mixed shapes in flight

@@ -193,6 +193,7 @@ qrcp_opts defaults() {
   o.sketch_precision = 0;
   o.trailing_precision = 0;
   o.pivot_base = 0;
+  o.pivot_steps = 0;
   return o;
 }
 
@@ -204,6 +205,7 @@ qrcp_opts read_opts(const qrcp_opts* p) {
   if (sz >= (int)(offsetof(qrcp_opts, sketch_precision) + 4)) o.sketch_precision = p->sketch_precision;
   if (sz >= (int)(offsetof(qrcp_opts, trailing_precision) + 4)) o.trailing_precision = p->trailing_precision;
   if (sz >= (int)(offsetof(qrcp_opts, pivot_base) + 4)) o.pivot_base = p->pivot_base;
+  if (sz >= (int)(offsetof(qrcp_opts, pivot_steps) + 4)) o.pivot_steps = p->pivot_steps;
   return o;
 }
 
@@ -359,6 +361,7 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
   if (o.sketch_precision < 0 || o.sketch_precision > 1) return -12;
   if (o.trailing_precision < 0 || o.trailing_precision > 1) return -12;
   if (o.pivot_base != 0 && o.pivot_base != 1) return -12;
+  if (o.pivot_steps != 0 && o.pivot_steps != 1) return -12;
   if (m < n) return QRCP_ERR_UNSUPPORTED;
   *rank = 0;
   if (n == 0) return QRCP_OK;
@@ -367,7 +370,8 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
   if (!tau) return -10;
   const i64 b = std::min<i64>(block_size, n);
   const int d = sketch_rows(block_size, sketch_factor);
-  if (d > 1024 || n > 65536) return QRCP_ERR_UNSUPPORTED;
+  // the pivot selection of the first block (n_i = n) must fit its resident grid
+  if (d > 1024 || lu_resident_groups(n) == 0) return QRCP_ERR_UNSUPPORTED;
   FactorWs w;
   const size_t need = carve_factor(nullptr, m, n, b, d, &w);
   if (!workspace || workspace_bytes < need) return QRCP_ERR_WORKSPACE;
@@ -415,21 +419,22 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
   int cur = 0;
   i64 ell = 0;
   int status = QRCP_OK;
-  // QRCP_LU_ALLSTEPS=1 runs every elimination step of the pivot selection (the
-  // full GETRF of the sketch); the selected columns and factors are the same
-  const bool lu_all_steps = getenv("QRCP_LU_ALLSTEPS") != nullptr;
+  // pivot_steps = 1 runs only the block's k_max elimination steps of the
+  // GETRF of the sketch (the selected columns are the same; the order of the
+  // columns no block selects is not that of Alg. 2)
+  const bool lu_all_steps = o.pivot_steps == 0;
   for (i64 s = 0; s < n; ) {
     const i64 ni = n - s, mi = m - s;
     const int kmax = (int)std::min<i64>(b, std::min(ni, mi));
     const i64 c = s + kmax;
     double* Ablk = A + s + s * lda;  // panel top-left (rows s.., physical column s)
-    // 1. pivots of the sketch (Alg. 2 GETRF on the transpose).  Only the first
-    // kmax elimination steps run: partial pivoting at step j depends on the
-    // steps before j alone, so they fix the kmax selected columns, and the
-    // later steps would only reorder the columns this block leaves, which the
-    // next block selects among again.
+    // 1. pivots of the sketch (Alg. 2 GETRF on the transpose), all min(d, n_i)
+    // elimination steps by default.  With pivot_steps = 1 only the first kmax
+    // run: partial pivoting at step j depends on the steps before j alone, so
+    // they fix the kmax selected columns, and the later steps only reorder the
+    // columns this block leaves, which the next block selects among again.
     {
-      ProfScope ps(kStLu, 2.0 * ni * d * kmax, st);
+      ProfScope ps(kStLu, 2.0 * ni * d * (lu_all_steps ? std::min<i64>(d, ni) : kmax), st);
       QRCP_TRY(launch_lu_pivots(w.sk0 + s * d, d, ni, d, w.xw, w.rec, w.rec_bytes, w.ipiv, w.jsk,
                                 w.status, st, lu_all_steps ? 0 : kmax));
     }
@@ -900,6 +905,33 @@ int qrcp_sketch_update(double* Rsk, int64_t d, int64_t b, int64_t nt, int64_t ld
   const int bb = (int)b;
   QRCP_TRY(launch_trinv_upper(R11, ldr11, bb, Rinv, b, st));
   QRCP_TRY(gemm(false, false, Prec::F64, ga(bb, bb, bb, Rsk, ldrsk, Rinv, b, X, b), nullptr, 0, st));
+  QRCP_TRY(gemm(false, false, Prec::F64,
+                ga(bb, (int)nt, bb, X, b, R12, ldr12, Rsk + b * ldrsk, ldrsk, -1.0, 1.0), nullptr, 0, st));
+  QRCP_HIP(hipStreamSynchronize(st));
+  return QRCP_OK;
+}
+
+int qrcp_sketch_update_chol(double* Rsk, int64_t d, int64_t b, int64_t nt, int64_t ldrsk,
+                            const double* Rc, int64_t ldrc, const double* dsig, const double* R12,
+                            int64_t ldr12, void* workspace, size_t workspace_bytes, void* stream) {
+  if (d < 1) return -2;
+  if (b < 1 || b > d) return -3;
+  if (nt < 0) return -4;
+  if (ldrsk < d) return -5;
+  if (ldrc < b) return -7;
+  if (ldr12 < b) return -10;
+  if (nt == 0) return QRCP_OK;
+  if (b > 1024) return QRCP_ERR_UNSUPPORTED;
+  const size_t need = 2 * (size_t)b * b * 8 + 4 * kAlign;
+  if (!workspace || workspace_bytes < need) return QRCP_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  Carver c{(char*)workspace};
+  double* Rinv = c.take<double>((size_t)b * b);
+  double* X = c.take<double>((size_t)b * b);
+  const int bb = (int)b;
+  // the kernels of qrcp_factor's one-pass sample update: X = Rc^{-1} diag(D)
+  QRCP_TRY(launch_trinv_upper(Rc, ldrc, bb, Rinv, b, st));
+  QRCP_TRY(launch_scale_upper_cols(Rinv, b, dsig, bb, X, b, st));
   QRCP_TRY(gemm(false, false, Prec::F64,
                 ga(bb, (int)nt, bb, X, b, R12, ldr12, Rsk + b * ldrsk, ldrsk, -1.0, 1.0), nullptr, 0, st));
   QRCP_HIP(hipStreamSynchronize(st));

@@ -186,6 +186,11 @@ int qrcp_server_submit(qrcp_server* s, const qrcp_request* req, uint64_t* ticket
       !(r.sketch_factor >= 1.0) || !(r.tol >= 0.0) || (!r.A && r.m * r.n > 0))
     return -2;
   if (r.m < r.n) return QRCP_ERR_UNSUPPORTED;
+  // the same up-front limits as qrcp_factor: sketch rows and the pivot
+  // selection's resident grid for the first block
+  if (r.n > 0 && (std::ceil(r.sketch_factor * (double)r.block_size - 1e-12) > 1024.0 ||
+                  qrcp::lu_resident_groups(r.n) == 0))
+    return QRCP_ERR_UNSUPPORTED;
   const size_t ws = qrcp_workspace_size(r.m, r.n, r.block_size, r.sketch_factor, &r.opts);
   const int groups = qrcp::request_groups(r);
   if ((int64_t)ws > s->budget || groups > s->cu_budget) return QRCP_ERR_UNSUPPORTED;

@@ -39,7 +39,7 @@ _i64, _u64, _i32, _u32, _dbl, _sz, _vp = (ctypes.c_int64, ctypes.c_uint64, ctype
 class QrcpOpts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("cholqr_passes", ctypes.c_int32),
                 ("sketch_precision", ctypes.c_int32), ("trailing_precision", ctypes.c_int32),
-                ("pivot_base", ctypes.c_int32)]
+                ("pivot_base", ctypes.c_int32), ("pivot_steps", ctypes.c_int32)]
 
 
 def _sig(name, res, *args):
@@ -70,6 +70,8 @@ _sig("qrcp_reconstruct", ctypes.c_int, _vp, _i64, _i64, _i64, _vp, _vp, _vp, _sz
 _sig("qrcp_apply_qt_workspace_size", _sz, _i64, _i64, _i64)
 _sig("qrcp_apply_qt", ctypes.c_int, _vp, _i64, _i64, _i64, _vp, _vp, _i64, _i64, _i32, _vp, _sz, _vp)
 _sig("qrcp_sketch_update", ctypes.c_int, _vp, _i64, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp)
+_sig("qrcp_sketch_update_chol", ctypes.c_int, _vp, _i64, _i64, _i64, _i64, _vp, _i64, _vp, _vp, _i64,
+     _vp, _sz, _vp)
 
 
 
@@ -111,7 +113,7 @@ EXPORTED = ["qrcp_profile_enable", "qrcp_profile_num_stages", "qrcp_profile_stag
             "qrcp_sketch", "qrcp_lu_workspace_size", "qrcp_lu_pivots",
             "qrcp_sketch_qr_workspace_size", "qrcp_sketch_qr", "qrcp_panel_workspace_size",
             "qrcp_cholqr", "qrcp_reconstruct", "qrcp_apply_qt_workspace_size", "qrcp_apply_qt",
-            "qrcp_sketch_update", "qrcp_server_create", "qrcp_server_submit", "qrcp_server_poll",
+            "qrcp_sketch_update", "qrcp_sketch_update_chol", "qrcp_server_create", "qrcp_server_submit", "qrcp_server_poll",
             "qrcp_server_wait", "qrcp_server_pending", "qrcp_server_destroy"]
 
 
@@ -160,9 +162,10 @@ def _ws(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 
 
-def _opts(cholqr_passes=1, sketch_precision=0, trailing_precision=0, pivot_base=0) -> QrcpOpts:
+def _opts(cholqr_passes=1, sketch_precision=0, trailing_precision=0, pivot_base=0,
+          pivot_steps=0) -> QrcpOpts:
     return QrcpOpts(ctypes.sizeof(QrcpOpts), cholqr_passes, sketch_precision, trailing_precision,
-                    pivot_base)
+                    pivot_base, pivot_steps)
 
 
 # ---------------------------------------------------------------- full method
@@ -173,11 +176,11 @@ def workspace_size(m, n, block_size, sketch_factor=1.25, **opts) -> int:
 
 def factor(A: torch.Tensor, block_size: int, sketch_factor: float = 1.25, seed: int = 42,
            tol: float = 0.0, *, cholqr_passes: int = 1, sketch_precision: int = 0,
-           trailing_precision: int = 0, pivot_base: int = 0, workspace: torch.Tensor | None = None,
-           stream=None):
+           trailing_precision: int = 0, pivot_base: int = 0, pivot_steps: int = 0,
+           workspace: torch.Tensor | None = None, stream=None):
     """qrcp_factor: A (m x n, column-major, overwritten) -> (A, jpiv, tau, rank)."""
     ptr, m, n, lda = _cm(A, "A")
-    o = _opts(cholqr_passes, sketch_precision, trailing_precision, pivot_base)
+    o = _opts(cholqr_passes, sketch_precision, trailing_precision, pivot_base, pivot_steps)
     need = int(_lib.qrcp_workspace_size(m, n, block_size, sketch_factor, ctypes.byref(o)))
     if workspace is None:
         workspace = _ws(need, A.device)
@@ -297,6 +300,20 @@ def sketch_update(Rsk: torch.Tensor, b: int, R11: torch.Tensor, R12: torch.Tenso
     return Rsk
 
 
+def sketch_update_chol(Rsk: torch.Tensor, b: int, Rc: torch.Tensor, dsig: torch.Tensor,
+                       R12: torch.Tensor) -> torch.Tensor:
+    """The one-pass form of the sample update: Rsk12 - Rc^{-1} diag(D) R12."""
+    ptr, d, cols, ld = _cm(Rsk, "Rsk")
+    pc, _, _, ldc = _cm(Rc, "Rc")
+    p12, _, nt, ld12 = _cm(R12, "R12")
+    assert cols == b + nt and dsig.is_cuda and dsig.dtype == torch.float64
+    ws = _ws(2 * b * b * 8 + 2048, Rsk.device)
+    _check(_lib.qrcp_sketch_update_chol(ptr, d, b, nt, ld, pc, ldc, dsig.data_ptr(), p12, ld12,
+                                        ws.data_ptr(), ws.numel(), _stream()),
+           "qrcp_sketch_update_chol")
+    return Rsk
+
+
 # ---------------------------------------------------------------- timing
 def profile_enable(mode: int) -> None:
     _check(_lib.qrcp_profile_enable(mode), "qrcp_profile_enable")
@@ -335,7 +352,7 @@ class Server:
     def submit(self, A: torch.Tensor, block_size: int, sketch_factor: float = 1.25,
                seed: int = 42, tol: float = 0.0, *, cholqr_passes: int = 1,
                sketch_precision: int = 0, trailing_precision: int = 0,
-               pivot_base: int = 0) -> int:
+               pivot_base: int = 0, pivot_steps: int = 0) -> int:
         ptr, m, n, lda = _cm(A, "A")
         jpiv = torch.empty(n, dtype=torch.int64, device=A.device)
         tau = torch.empty(min(m, n), dtype=torch.float64, device=A.device)
@@ -344,7 +361,8 @@ class Server:
         torch.cuda.current_stream(A.device).synchronize()
         req = Request(ctypes.sizeof(Request), m, n, lda, block_size, sketch_factor, seed, tol,
                       ptr, jpiv.data_ptr(), tau.data_ptr(),
-                      _opts(cholqr_passes, sketch_precision, trailing_precision, pivot_base))
+                      _opts(cholqr_passes, sketch_precision, trailing_precision, pivot_base,
+                            pivot_steps))
         t = _u64(0)
         _check(_lib.qrcp_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)),
                "qrcp_server_submit")

@@ -61,8 +61,19 @@ def test_illegal_arguments_rejected_before_launch(lib):
     assert L.qrcp_factor(nul, 4, 8, 4, 2, 1.25, 1, 0.0, nul, nul, ctypes.byref(r), None, nul, 0, nul) == lib.QRCP_ERR_UNSUPPORTED
     assert L.qrcp_factor(nul, 4, 0, 4, 2, 1.25, 1, 0.0, nul, nul, ctypes.byref(r), None, nul, 0, nul) == 0
     # bad options
-    o = lib.QrcpOpts(ctypes.sizeof(lib.QrcpOpts), 3, 0, 0, 0)
+    o = lib.QrcpOpts(ctypes.sizeof(lib.QrcpOpts), 3, 0, 0, 0, 0)
     assert L.qrcp_factor(nul, 8, 4, 8, 2, 1.25, 1, 0.0, nul, nul, ctypes.byref(r), ctypes.byref(o), nul, 0, nul) == -12
+    o = lib.QrcpOpts(ctypes.sizeof(lib.QrcpOpts), 1, 0, 0, 0, 2)
+    assert L.qrcp_factor(nul, 8, 4, 8, 2, 1.25, 1, 0.0, nul, nul, ctypes.byref(r), ctypes.byref(o), nul, 0, nul) == -12
+    # n above the pivot selection's resident grid (32768 columns) is refused
+    # in the argument check, before any launch or workspace use
+    fake = ctypes.c_void_p(16)
+    assert L.qrcp_factor(fake, 40000, 40000, 40000, 256, 1.25, 1, 0.0, fake, fake, ctypes.byref(r), None,
+                         nul, 0, nul) == lib.QRCP_ERR_UNSUPPORTED
+    assert L.qrcp_factor(fake, 32768, 32768, 32768, 256, 1.25, 1, 0.0, fake, fake, ctypes.byref(r), None,
+                         nul, 0, nul) == lib.QRCP_ERR_WORKSPACE
+    assert L.qrcp_factor(fake, 512, 512, 512, 1000, 1.25, 1, 0.0, fake, fake, ctypes.byref(r), None,
+                         nul, 0, nul) == lib.QRCP_ERR_UNSUPPORTED
     # missing workspace is reported, not dereferenced
     fake = ctypes.c_void_p(16)
     assert L.qrcp_factor(fake, 8, 4, 8, 2, 1.25, 1, 0.0, fake, fake, ctypes.byref(r), None, nul, 0, nul) == lib.QRCP_ERR_WORKSPACE
@@ -70,3 +81,4 @@ def test_illegal_arguments_rejected_before_launch(lib):
     assert L.qrcp_geqrf(nul, 8, 4, 2, nul, 2, nul, 0, nul) == -4
     assert L.qrcp_lu_pivots(nul, 0, 4, 4, nul, nul, nul, 0, nul) == -2
     assert L.qrcp_sketch_update(nul, 8, 9, 4, 8, nul, 8, nul, 8, nul, 0, nul) == -3
+    assert L.qrcp_sketch_update_chol(nul, 8, 9, 4, 8, nul, 8, nul, nul, 8, nul, 0, nul) == -3

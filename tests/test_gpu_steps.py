@@ -128,13 +128,14 @@ def test_sketch_qr_zero_column(Q):
 
 
 # ---- a7-a8: preconditioned Cholesky QR -----------------------------------------
-@pytest.mark.parametrize("passes", [1, 2])
-def test_cholqr_matches_oracle(Q, passes):
+@pytest.mark.parametrize("mi,k,passes", [(3000, 64, 1), (3000, 64, 2), (4000, 256, 1), (4000, 256, 2),
+                                         (1000, 200, 1)])
+def test_cholqr_matches_oracle(Q, mi, k, passes):
     # the preconditioner is the R factor of a sketch of the panel (as in the
-    # method), so M^pre is well conditioned and Q is determined to rounding
-    mi, k = 3000, 64
+    # method), so M^pre is well conditioned and Q is determined to rounding;
+    # k = 256 runs the blocked Cholesky over resident workgroups
     p = W.usv(mi, k, W.spectrum("geometric", k, lo=1e-6), seed=4)
-    rs = np.linalg.qr(O.sketch_operator(80, mi, 5) @ p, mode="r")
+    rs = np.linalg.qr(O.sketch_operator(int(1.25 * k), mi, 5) @ p, mode="r")
     mpre = O.solve_triangular(rs, p.T, trans="T", lower=False).T
     qr_, rc_, keff_ = O.cholqr(mpre, passes)
     P, rc, keff = Q.cholqr(dev(p), dev(rs), passes)
@@ -200,3 +201,24 @@ def test_sketch_update_matches_formula(Q):
     ref[:b, b:] = rsk[:b, b:] - x @ r12
     got = host(Q.sketch_update(dev(rsk), b, dev(r11), dev(r12)))
     assert np.max(np.abs(got - ref)) < 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("d,b,nt", [(80, 64, 300), (320, 256, 2000)])
+def test_sketch_update_one_pass_form(Q, d, b, nt):
+    """The form qrcp_factor uses after one Cholesky QR pass, Rc^{-1} diag(D) R12,
+    against the paper's Rsk12 - Rsk11 R11^{-1} R12 with R11 = diag(D) Rc Rsk11
+    (Alg. 3's R11 with the signs of the reconstruction)."""
+    rng = np.random.default_rng(d + b)
+    rsk = np.triu(W.gaussian(d, b + nt, seed=11))
+    rsk[np.arange(b), np.arange(b)] = np.abs(rsk[np.arange(b), np.arange(b)]) + 4.0
+    rc = np.triu(W.gaussian(b, b, seed=12)) * 0.05
+    rc[np.arange(b), np.arange(b)] = 1.0 + 0.1 * np.abs(rc[np.arange(b), np.arange(b)])
+    dsig = rng.choice([-1.0, 1.0], size=b)
+    r12 = W.gaussian(b, nt, seed=13)
+    r11 = dsig[:, None] * (rc @ rsk[:b, :b])
+    x = O.solve_triangular(r11, rsk[:b, :b].T, trans="T", lower=False).T   # Rsk11 R11^{-1}
+    ref = np.array(rsk)
+    ref[:b, b:] = rsk[:b, b:] - x @ r12
+    got = host(Q.sketch_update_chol(dev(rsk), b, dev(rc), torch.from_numpy(dsig).cuda(), dev(r12)))
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.abs(ref).max() * np.sqrt(b)
+    assert np.array_equal(got[:, :b], rsk[:, :b])
