@@ -128,8 +128,9 @@ def sketch(a: np.ndarray, d: int, seed: int, precision: str = "f64") -> np.ndarr
 # qrcp_wide by LU (Alg. 2): GETRF on the transposed sketch, pivot format
 # conversion, column permutation, GEQRF of the permuted sketch.
 # --------------------------------------------------------------------------
-def getrf_pivots(x: np.ndarray):
-    """Row-pivoted LU (GETRF semantics) of x (r x c), unblocked right-looking.
+def getrf_pivots(x: np.ndarray, steps: int | None = None):
+    """Row-pivoted LU (GETRF semantics) of x (r x c), unblocked right-looking,
+    over the first ``steps`` columns (all min(r, c) by default).
 
     Step j picks p = argmax_{t >= j} |x(t, j)| (ties -> smallest t, as IDAMAX),
     swaps rows j and p, and, if the pivot is nonzero, scales the column below
@@ -141,7 +142,7 @@ def getrf_pivots(x: np.ndarray):
     """
     x = np.array(x, dtype=np.float64, copy=True)
     r, c = x.shape
-    steps = min(r, c)
+    steps = min(r, c) if steps is None else min(r, c, steps)
     ipiv = np.empty(steps, dtype=np.int64)
     margins = np.ones(steps)
     for j in range(steps):
@@ -209,28 +210,39 @@ def householder_qr(a: np.ndarray):
     return np.triu(a), v_all, tau
 
 
-def qrcp_wide_lu(msk: np.ndarray):
+def qrcp_wide_lu(msk: np.ndarray, steps: int | None = None):
     """Alg. 2: pivots of the wide sketch by GETRF on its transpose, the
     pivot-format conversion, the column permutation, then GEQRF.
+
+    ``steps`` bounds the elimination steps by the rank the sketch can have:
+    the sketch of a matrix with m_i rows has rank at most m_i, so beyond
+    m_i steps the Schur complement of its transpose is zero in exact
+    arithmetic and GETRF would pivot on rounding noise (only a wide matrix's
+    last blocks have m_i < min(d, n_i)).
 
     Returns (Jsk, Rsk, ipiv, margins).  Rsk is min(d, n_i) x n_i upper
     trapezoidal; Q^sk is not needed by BQRRP and is discarded."""
     d, ni = msk.shape
-    ipiv, margins = getrf_pivots(msk.T)
+    ipiv, margins = getrf_pivots(msk.T, steps)
     jsk = piv_transform(ipiv, ni)
     rsk, _, _ = householder_qr(msk[:, jsk])
     return jsk, rsk[: min(d, ni)], ipiv, margins
 
 
-def qrcp_wide_geqp3(msk: np.ndarray):
+def qrcp_wide_geqp3(msk: np.ndarray, steps: int | None = None):
     """The alternative qrcp_wide: Businger-Golub column-norm pivoting of the
-    sketch (GEQP3 semantics, norms recomputed exactly each step)."""
+    sketch (GEQP3 semantics, norms recomputed exactly each step).  Only the
+    first ``steps`` Householder steps pivot (the same rank bound as
+    ``qrcp_wide_lu``); the rest keep the column order."""
     d, ni = msk.shape
     a = np.array(msk, dtype=np.float64, copy=True)
     jsk = np.arange(ni)
+    psteps = min(d, ni) if steps is None else min(d, ni, steps)
     for j in range(min(d, ni)):
-        norms = np.linalg.norm(a[j:, j:], axis=0)
-        p = j + int(np.argmax(norms))
+        p = j
+        if j < psteps:
+            norms = np.linalg.norm(a[j:, j:], axis=0)
+            p = j + int(np.argmax(norms))
         if p != j:
             a[:, [j, p]] = a[:, [p, j]]
             jsk[[j, p]] = jsk[[p, j]]
@@ -369,26 +381,37 @@ class Result:
 def bqrrp(a: np.ndarray, b: int, gamma: float = 1.25, seed: int = 42, tol: float = 0.0,
           cholqr_passes: int = 1, qrcp_wide: str = "lu", sketch_precision: str = "f64",
           trailing_precision: str = "f64", msk: np.ndarray | None = None,
-          trace_sketch: bool = False, max_blocks: int | None = None) -> Result:
-    """BQRRP with LU-based qrcp_wide and Cholesky-QR qr_tall.
+          trace_sketch: bool = False, max_blocks: int | None = None,
+          qr_tall: str = "cholqr", max_rank: int | None = None) -> Result:
+    """BQRRP (Alg. 1) with a choice of qrcp_wide (LU, Alg. 2, or GEQP3 on the
+    sketch) and of qr_tall (preconditioned Cholesky QR + reconstruction,
+    Alg. 3, or Householder QR of the panel, GEQRF; Sec. 2.3).
 
-    Per block i (s = i b, n_i = n - s, m_i = m - s, k_max = min(b, n_i, m_i)):
+    Per block i (s = i b, n_i = n - s, m_i = m - s,
+    k_max = min(b, n_i, m_i, max_rank - s)):
       1. [Jsk, Rsk] = qrcp_wide(M^sk(:, s:))                      (Alg. 1, Alg. 2)
       2. k = tri_rank(Rsk)                                       (Sec. 2.2)
       3. permute M(:, s:) (all m rows) and J(s:) by Jsk          (Sec. 3)
       4. k = 0: stop with rank s
-      5. M^pre = M(s:, s:s+k) Rsk(0:k,0:k)^{-1}; Cholesky QR; a breakdown at
-         column t truncates k to t                               (Alg. 3)
+      5. qr_tall = cholqr: M^pre = M(s:, s:s+k) Rsk(0:k,0:k)^{-1}; Cholesky
+         QR; a breakdown at column t truncates k to t             (Alg. 3)
       6. Householder reconstruction -> Y, tau, D;
          R11 = diag(D) R^chol Rsk(0:k, 0:k)                      (Alg. 3, rows signed by D)
+         (qr_tall = geqrf: Y, tau and R11 from GEQRF of M(s:, s:s+k))
       7. apply (I - Y T Y^T)^T to M(s:m, s+k:n)                  (Sec. 2.4, ORMQR)
-      8. k < k_max or s + k_max = n: stop with rank s + k
+      8. k < k_max or s + k_max = min(m, n, max_rank): stop with rank s + k
       9. M^sk(:, c:) = [Rsk12 - Rsk11 R11^{-1} R12; Rsk22]        (Alg. 1, Sec. 3)
+
+    Any aspect ratio (Sec. 1.3): for m < n the loop ends after the block that
+    reaches row m, and R is m x n upper trapezoidal.  ``max_rank`` (truncated
+    output): the loop stops once max_rank columns are factored; the last block
+    factors only the columns up to max_rank, and A(l:, l:) keeps the residual.
     """
     a = np.array(a, dtype=np.float64, order="F", copy=True)
     m, n = a.shape
-    if m < n:
-        raise NotImplementedError("m < n")
+    if qr_tall not in ("cholqr", "geqrf"):
+        raise ValueError(qr_tall)
+    lim = min(m, n) if max_rank is None else min(m, n, max(int(max_rank), 0))
     d = int(math.ceil(gamma * b - 1e-12))
     if msk is None:
         msk = sketch(a, d, seed, sketch_precision)
@@ -399,9 +422,9 @@ def bqrrp(a: np.ndarray, b: int, gamma: float = 1.25, seed: int = 42, tol: float
     ref = math.sqrt(float(np.max(np.sum(msk * msk, axis=0)))) if n else 0.0
     res = Result(a=a, jpiv=jpiv, tau=tau, rank=0)
     s = 0
-    while s < n:
+    while s < lim:
         ni, mi = n - s, m - s
-        kmax = min(b, ni, mi)
+        kmax = min(b, ni, mi, lim - s)
         c = s + kmax
         cur = msk[:, s:]
         if not np.all(np.isfinite(cur)):
@@ -409,9 +432,9 @@ def bqrrp(a: np.ndarray, b: int, gamma: float = 1.25, seed: int = 42, tol: float
             res.rank = s
             return res
         if qrcp_wide == "lu":
-            jsk, rsk, ipiv, margins = qrcp_wide_lu(cur)
+            jsk, rsk, ipiv, margins = qrcp_wide_lu(cur, min(d, ni, mi))
         else:
-            jsk, rsk, ipiv, margins = qrcp_wide_geqp3(cur)
+            jsk, rsk, ipiv, margins = qrcp_wide_geqp3(cur, min(d, ni, mi))
         k = tri_rank(rsk, kmax, tol, ref)
         a[:, s:] = a[:, s + jsk]
         jpiv[s:] = jpiv[s + jsk]
@@ -421,25 +444,33 @@ def bqrrp(a: np.ndarray, b: int, gamma: float = 1.25, seed: int = 42, tol: float
         if k == 0:
             res.rank = s
             return res
-        # ---- panel: preconditioned Cholesky QR (Alg. 3) ----
-        while True:
-            mpre = solve_triangular(rsk[:k, :k], a[s:, s:s + k].T, trans="T", lower=False).T
-            q, rc, keff = cholqr(mpre, cholqr_passes)
-            if keff == k:
-                break
-            k = keff              # breakdown: redo with the leading keff columns
-            if k == 0:
-                tr.k = 0
-                res.rank = s
-                return res
+        if qr_tall == "geqrf":
+            # ---- panel: Householder QR (GEQRF) of M(s:m, s:s+k) (Sec. 2.3) ----
+            rp, y, tk = householder_qr(a[s:, s:s + k])
+            blk = a[s:, s:s + k]
+            blk[:, :] = np.tril(y, -1)
+            blk[:k, :k] += np.triu(rp[:k, :k])
+            tau[s:s + k] = tk
+        else:
+            # ---- panel: preconditioned Cholesky QR (Alg. 3) ----
+            while True:
+                mpre = solve_triangular(rsk[:k, :k], a[s:, s:s + k].T, trans="T", lower=False).T
+                q, rc, keff = cholqr(mpre, cholqr_passes)
+                if keff == k:
+                    break
+                k = keff              # breakdown: redo with the leading keff columns
+                if k == 0:
+                    tr.k = 0
+                    res.rank = s
+                    return res
+            y, tk, dsig, _ = householder_reconstruct(q)
+            r11 = dsig[:, None] * (rc @ rsk[:k, :k])
+            # write Y below the diagonal and R11 on/above it
+            blk = a[s:, s:s + k]
+            blk[:, :] = y
+            blk[:k, :k] = np.triu(r11) + np.tril(y[:k, :k], -1)
+            tau[s:s + k] = tk
         tr.k = k
-        y, tk, dsig, _ = householder_reconstruct(q)
-        r11 = dsig[:, None] * (rc @ rsk[:k, :k])
-        # write Y below the diagonal and R11 on/above it
-        blk = a[s:, s:s + k]
-        blk[:, :] = y
-        blk[:k, :k] = np.triu(r11) + np.tril(y[:k, :k], -1)
-        tau[s:s + k] = tk
         # ---- trailing update M(s:m, s+k:n) <- Q^T M(s:m, s+k:n) ----
         if s + k < n:
             t = larft(y, tk)
@@ -452,7 +483,7 @@ def bqrrp(a: np.ndarray, b: int, gamma: float = 1.25, seed: int = 42, tol: float
                 a[s:, s + k:] = cmat - (y32 @ w).astype(np.float64)
             else:
                 a[s:, s + k:] = apply_qt(y, t, cmat)
-        if k < kmax or c >= n:
+        if k < kmax or c >= lim:
             res.rank = s + k
             return res
         if max_blocks is not None and len(res.trace) >= max_blocks:
@@ -471,7 +502,7 @@ def bqrrp(a: np.ndarray, b: int, gamma: float = 1.25, seed: int = 42, tol: float
         new[b:rows] = np.triu(rsk[b:rows, b:])
         msk[:, c:] = new
         s = c
-    res.rank = min(m, n)
+    res.rank = lim
     return res
 
 
