@@ -35,7 +35,7 @@ enum {
   QRCP_ERR_WORKSPACE = 1,   /* workspace missing or smaller than required       */
   QRCP_ERR_HIP = 2,         /* a HIP runtime call or kernel launch failed        */
   QRCP_ERR_NONFINITE = 3,   /* NaN/Inf in the input or in the sketch             */
-  QRCP_ERR_UNSUPPORTED = 4, /* valid but not implemented (e.g. m < n)            */
+  QRCP_ERR_UNSUPPORTED = 4, /* valid but not implemented (e.g. d > 1024)         */
   QRCP_ERR_TIMEOUT = 5      /* a cross-workgroup wait exceeded its spin limit     */
 };
 
@@ -58,6 +58,15 @@ typedef struct qrcp_opts {
                                  that no block selects (the residual block after an
                                  early exit) come out in another order, and R agrees
                                  with the default only to rounding                      */
+  int32_t qr_tall;            /* panel QR: 0 = preconditioned Cholesky QR + Householder
+                                 reconstruction (Alg. 3, default); 1 = Householder QR
+                                 of the panel, GEQRF (Sec. 2.3; m <= 65536)             */
+  int32_t qrcp_wide;          /* pivots of the sketch: 0 = LU (Alg. 2, default);
+                                 1 = column-norm pivoted QR of the sketch (GEQP3)       */
+  int64_t max_rank;           /* 0 = no limit (default); l > 0: truncated output, the
+                                 loop stops once l columns are factored (the last block
+                                 factors only up to column l); rank <= l and
+                                 A(rank:, rank:) holds the residual block               */
 } qrcp_opts;
 
 /* Bytes of DEVICE workspace qrcp_factor needs for these sizes and options. */
@@ -73,7 +82,8 @@ size_t qrcp_workspace_size(int64_t m, int64_t n, int64_t block_size, double sket
  *          diagonal, the Householder vectors (implicit unit head) below it for
  *          the first `rank` columns, and the residual block A(rank:, rank:)
  *          when rank < n.
- *  m, n    m >= n >= 0 (m < n returns QRCP_ERR_UNSUPPORTED).
+ *  m, n    >= 0, any aspect ratio (Sec. 1.3): for m < n the loop ends after
+ *          the block that reaches row m and R is m x n upper trapezoidal.
  *  block_size   b >= 1.
  *  sketch_factor gamma >= 1; the sketch has d = ceil(gamma*b) rows
  *          (d <= 1024 and n <= 32768, else QRCP_ERR_UNSUPPORTED, returned
@@ -239,7 +249,7 @@ typedef struct qrcp_result {
 /* NULL on failure (bad config, no device). */
 qrcp_server* qrcp_server_create(const qrcp_server_cfg* cfg);
 /* Queues a request; *ticket identifies it.  -i: i-th argument illegal;
- * QRCP_ERR_UNSUPPORTED if it can never be admitted (m < n, workspace above the
+ * QRCP_ERR_UNSUPPORTED if it can never be admitted (workspace above the
  * budget, resident grid above the device). */
 int qrcp_server_submit(qrcp_server* s, const qrcp_request* req, uint64_t* ticket);
 /* 0 = done (*out filled, ticket released), 1 = pending, -2 = unknown ticket. */

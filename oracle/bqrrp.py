@@ -238,11 +238,17 @@ def qrcp_wide_geqp3(msk: np.ndarray, steps: int | None = None):
     a = np.array(msk, dtype=np.float64, copy=True)
     jsk = np.arange(ni)
     psteps = min(d, ni) if steps is None else min(d, ni, steps)
+    margins = np.ones(psteps)
     for j in range(min(d, ni)):
         p = j
         if j < psteps:
             norms = np.linalg.norm(a[j:, j:], axis=0)
             p = j + int(np.argmax(norms))
+            # relative gap to the runner-up (as for the LU pivots)
+            if norms.size > 1 and norms[p - j] > 0:
+                margins[j] = (norms[p - j] - np.max(np.delete(norms, p - j))) / norms[p - j]
+            elif norms.size > 1:
+                margins[j] = 0.0
         if p != j:
             a[:, [j, p]] = a[:, [p, j]]
             jsk[[j, p]] = jsk[[p, j]]
@@ -253,7 +259,7 @@ def qrcp_wide_geqp3(msk: np.ndarray, steps: int | None = None):
             a[j:, j + 1:] -= t * np.outer(vv, w)
         a[j, j] = beta
         a[j + 1:, j] = 0.0
-    return jsk, np.triu(a)[: min(d, ni)], None, np.ones(min(d, ni))
+    return jsk, np.triu(a)[: min(d, ni)], None, margins
 
 
 # --------------------------------------------------------------------------

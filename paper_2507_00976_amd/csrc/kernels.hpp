@@ -84,6 +84,8 @@ int launch_any_nonfinite(const double* X, i64 ld, i64 rows, i64 cols, int* flag,
 // max_steps > 0 stops the elimination after that many steps (ipiv[0:steps] and
 // the positions they imply); 0 runs all min(d, ni) steps.
 size_t lu_records_bytes(int d, i64 ni, int max_steps = 0);
+// the largest lu_records_bytes(d, n_i) over 1 <= n_i <= n (a factorization's blocks)
+size_t lu_records_bytes_upto(int d, i64 n);
 int launch_lu_pivots(const double* Msk, int d, i64 ni, i64 ld, double* Xw, uint64_t* rec,
                      size_t rec_bytes, i64* ipiv, i64* jsk, int* status_dev, hipStream_t st,
                      int max_steps = 0);
@@ -92,6 +94,14 @@ int launch_lu_pivots(const double* Msk, int d, i64 ni, i64 ld, double* Xw, uint6
 size_t sketch_qr_ws_bytes(int d, i64 ni);
 int run_sketch_qr(const double* B, int d, i64 ni, i64 ldb, double* R, i64 ldr, void* ws,
                   size_t ws_bytes, int* status_dev, hipStream_t st);
+
+// ---- column-pivoted QR of the sketch (GEQP3; the alternative wide QRCP) ----
+// Msk d x ni (ld) -> jsk (pivot order), R (upper trapezoid, zeros below; may
+// alias Msk); X is a d x ni work copy (ld d); only the first psteps steps pivot.
+size_t sketch_geqp3_ws_bytes(int d);
+int launch_sketch_geqp3(const double* Msk, int d, i64 ni, i64 ld, int psteps, double* X,
+                        double* R, i64 ldr, i64* jsk, void* ws, size_t ws_bytes, int* status,
+                        hipStream_t st);
 
 // ---- column bookkeeping ----
 // jsk -> new logical maps (ping-pong arrays) + the placement plan

@@ -682,6 +682,13 @@ size_t lu_records_bytes(int d, i64 ni, int max_steps) {
   return (size_t)steps * G * RW * sizeof(uint64_t);
 }
 
+size_t lu_records_bytes_upto(int d, i64 n) {
+  // records grow with n_i within each rows-per-lane regime, but the switch to
+  // two rows per lane above 64 x 64 rows halves the group count, so the
+  // largest need is at n itself or at the top of the one-row regime
+  return std::max(lu_records_bytes(d, n), lu_records_bytes(d, std::min<i64>(n, 64L * 64)));
+}
+
 int launch_lu_pivots(const double* Msk, int d, i64 ni, i64 ld, double* Xw, uint64_t* rec,
                      size_t rec_bytes, i64* ipiv, i64* jsk, int* status_dev, hipStream_t st,
                      int max_steps) {

@@ -145,16 +145,20 @@ struct FactorWs {
   double* split;
   void* skqr;
   size_t skqr_bytes;
+  uint64_t* hrec;
+  size_t hrec_bytes;
+  void* gq;
+  size_t gq_bytes;
 };
 
-size_t carve_factor(char* base, i64 m, i64 n, i64 b, int d, FactorWs* w) {
+size_t carve_factor(char* base, i64 m, i64 n, i64 b, int d, FactorWs* w, bool hqr = false) {
   Carver c{base};
   const i64 bb = std::max<i64>(b, 1);
   w->big = c.take<double>((size_t)std::max(m * (i64)d, m * n));
   w->sk0 = c.take<double>((size_t)d * n);
   w->sk1 = c.take<double>((size_t)d * n);
   w->xw = c.take<double>((size_t)d * n);
-  w->rec_bytes = lu_records_bytes(d, n);
+  w->rec_bytes = lu_records_bytes_upto(d, n);
   w->rec = c.take<uint64_t>(w->rec_bytes / 8 + 1);
   for (int i = 0; i < 2; ++i) {
     w->J[i] = c.take<i64>(n + 1);
@@ -179,6 +183,12 @@ size_t carve_factor(char* base, i64 m, i64 n, i64 b, int d, FactorWs* w) {
   w->split = c.take<double>(kSplitBytes / 8);
   w->skqr_bytes = sketch_qr_ws_bytes(d, n);
   w->skqr = c.take<char>(w->skqr_bytes);
+  // column-pivoted sketch QR scratch (qrcp_wide = 1): reflector scalars and arg-max partials
+  w->gq_bytes = sketch_geqp3_ws_bytes(d);
+  w->gq = c.take<char>(w->gq_bytes);
+  // exchange records of the Householder panel's leaf kernel (qr_tall = 1)
+  w->hrec_bytes = hqr ? hh_leaf_records_bytes(m) : 0;
+  w->hrec = hqr ? c.take<uint64_t>(w->hrec_bytes / 8 + 1) : nullptr;
   return c.off + kAlign;
 }
 
@@ -194,6 +204,9 @@ qrcp_opts defaults() {
   o.trailing_precision = 0;
   o.pivot_base = 0;
   o.pivot_steps = 0;
+  o.qr_tall = 0;
+  o.qrcp_wide = 0;
+  o.max_rank = 0;
   return o;
 }
 
@@ -206,6 +219,9 @@ qrcp_opts read_opts(const qrcp_opts* p) {
   if (sz >= (int)(offsetof(qrcp_opts, trailing_precision) + 4)) o.trailing_precision = p->trailing_precision;
   if (sz >= (int)(offsetof(qrcp_opts, pivot_base) + 4)) o.pivot_base = p->pivot_base;
   if (sz >= (int)(offsetof(qrcp_opts, pivot_steps) + 4)) o.pivot_steps = p->pivot_steps;
+  if (sz >= (int)(offsetof(qrcp_opts, qr_tall) + 4)) o.qr_tall = p->qr_tall;
+  if (sz >= (int)(offsetof(qrcp_opts, qrcp_wide) + 4)) o.qrcp_wide = p->qrcp_wide;
+  if (sz >= (int)(offsetof(qrcp_opts, max_rank) + 8)) o.max_rank = p->max_rank;
   return o;
 }
 
@@ -227,27 +243,38 @@ GemmArgs ga(int M, int N, int K, const double* A, i64 lda, const double* B, i64 
 
 // First half of (H_0..H_{k-1})^T C for a clean unit lower trapezoidal Y
 // (mi x k, ldy): T from the UT transform of Y^T Y, W = Y^T C, W2 = T^T W.
+// T of the compact WY form of (H_0..H_{k-1}) from the UT transform of Y^T Y.
+int apply_qt_t(const double* Y, i64 mi, int k, i64 ldy, const double* tau, double* G, double* T,
+               i64 ldk, double* split, size_t split_bytes, hipStream_t st) {
+  if (k <= 0 || mi <= 0) return QRCP_OK;
+  ProfScope ps(kStLarft, 2.0 * mi * k * k, st);
+  QRCP_TRY(gemm(true, false, Prec::F64, ga(k, k, (int)mi, Y, ldy, Y, ldy, G, ldk), split, split_bytes, st));
+  QRCP_TRY(launch_ut_tinv(G, ldk, tau, k, st));
+  QRCP_TRY(launch_trinv_upper(G, ldk, k, T, ldk, st));
+  QRCP_TRY(launch_ut_zero_diag(T, ldk, tau, k, st));
+  return QRCP_OK;
+}
+
+// W = Y^T C, W2 = -T^T W (so that the update is C += Y W2, accumulated onto C).
+int apply_qt_wt(const double* Y, i64 mi, int k, i64 ldy, const double* T, i64 ldk, const double* C,
+                i64 nc, i64 ldc, Prec prec, double* W, double* W2, double* split,
+                size_t split_bytes, hipStream_t st) {
+  if (k <= 0 || nc <= 0 || mi <= 0) return QRCP_OK;
+  ProfScope ps(kStTrailW, 2.0 * mi * k * nc + 2.0 * k * k * nc, st);
+  GemmArgs w = ga(k, (int)nc, (int)mi, Y, ldy, C, ldc, W, k);
+  w.kind = GemmKind::TrailingW;
+  QRCP_TRY(gemm(true, false, prec, w, split, split_bytes, st));
+  QRCP_TRY(gemm(true, false, prec, ga(k, (int)nc, k, T, ldk, W, k, W2, k, -1.0, 0.0), split,
+                split_bytes, st));
+  return QRCP_OK;
+}
+
 int apply_qt_w(const double* Y, i64 mi, int k, i64 ldy, const double* tau, const double* C,
                i64 nc, i64 ldc, Prec prec, double* G, double* T, i64 ldk, double* W, double* W2,
                double* split, size_t split_bytes, hipStream_t st) {
   if (k <= 0 || nc <= 0 || mi <= 0) return QRCP_OK;
-  {
-    ProfScope ps(kStLarft, 2.0 * mi * k * k, st);
-    QRCP_TRY(gemm(true, false, Prec::F64, ga(k, k, (int)mi, Y, ldy, Y, ldy, G, ldk), split, split_bytes, st));
-    QRCP_TRY(launch_ut_tinv(G, ldk, tau, k, st));
-    QRCP_TRY(launch_trinv_upper(G, ldk, k, T, ldk, st));
-    QRCP_TRY(launch_ut_zero_diag(T, ldk, tau, k, st));
-  }
-  {
-    ProfScope ps(kStTrailW, 2.0 * mi * k * nc + 2.0 * k * k * nc, st);
-    GemmArgs w = ga(k, (int)nc, (int)mi, Y, ldy, C, ldc, W, k);
-    w.kind = GemmKind::TrailingW;
-    QRCP_TRY(gemm(true, false, prec, w, split, split_bytes, st));
-    // W2 = -T^T W, so that the update is C += Y W2 (accumulated onto C)
-    QRCP_TRY(gemm(true, false, prec, ga(k, (int)nc, k, T, ldk, W, k, W2, k, -1.0, 0.0), split,
-                  split_bytes, st));
-  }
-  return QRCP_OK;
+  QRCP_TRY(apply_qt_t(Y, mi, k, ldy, tau, G, T, ldk, split, split_bytes, st));
+  return apply_qt_wt(Y, mi, k, ldy, T, ldk, C, nc, ldc, prec, W, W2, split, split_bytes, st);
 }
 
 // Second half, rows r0 .. r1 of C: C(r0:r1, :) += Y(r0:r1, :) W2 (W2 = -T^T Y^T C).
@@ -338,17 +365,27 @@ const char* qrcp_last_error(void) { return g_last_error.c_str(); }
 
 size_t qrcp_workspace_size(int64_t m, int64_t n, int64_t block_size, double sketch_factor,
                            const qrcp_opts* opts) {
-  (void)opts;
   if (m < 0 || n < 0 || block_size < 1 || !(sketch_factor >= 1.0)) return 0;
   FactorWs w;
   const int d = sketch_rows(block_size, sketch_factor);
-  return carve_factor(nullptr, m, n, std::min<i64>(block_size, std::max<i64>(n, 1)), d, &w);
+  const qrcp_opts o = read_opts(opts);
+  return carve_factor(nullptr, m, n, std::min<i64>(block_size, std::max<i64>(n, 1)), d, &w,
+                      o.qr_tall == 1);
 }
 
-int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size,
+}  // extern "C"
+
+namespace qrcp {
+namespace {
+
+// The factorization behind qrcp_factor.  lookahead:
+// run the deferred rank-k update on the library's second stream (created on
+// first use); without it every launch goes to the caller's stream in the same
+// order, with the same arithmetic (the results are bitwise the same).
+int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size,
                 double sketch_factor, uint64_t seed, double tol, int64_t* jpiv, double* tau,
                 int64_t* rank, const qrcp_opts* opts_in, void* workspace, size_t workspace_bytes,
-                void* stream) {
+                void* stream, bool lookahead) {
   if (m < 0) return -2;
   if (n < 0) return -3;
   if (lda < std::max<int64_t>(1, m)) return -4;
@@ -362,22 +399,35 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
   if (o.trailing_precision < 0 || o.trailing_precision > 1) return -12;
   if (o.pivot_base != 0 && o.pivot_base != 1) return -12;
   if (o.pivot_steps != 0 && o.pivot_steps != 1) return -12;
-  if (m < n) return QRCP_ERR_UNSUPPORTED;
+  if (o.qr_tall != 0 && o.qr_tall != 1) return -12;
+  if (o.qrcp_wide != 0 && o.qrcp_wide != 1) return -12;
+  if (o.max_rank < 0) return -12;
   *rank = 0;
   if (n == 0) return QRCP_OK;
-  if (!A) return -1;
+  if (!A && m > 0) return -1;
   if (!jpiv) return -9;
-  if (!tau) return -10;
+  if (!tau && m > 0) return -10;
   const i64 b = std::min<i64>(block_size, n);
   const int d = sketch_rows(block_size, sketch_factor);
   // the pivot selection of the first block (n_i = n) must fit its resident grid
   if (d > 1024 || lu_resident_groups(n) == 0) return QRCP_ERR_UNSUPPORTED;
+  // the Householder panel's leaf kernel keeps one row per thread resident
+  if (o.qr_tall == 1 && m > 65536) return QRCP_ERR_UNSUPPORTED;
   FactorWs w;
-  const size_t need = carve_factor(nullptr, m, n, b, d, &w);
+  const size_t need = carve_factor(nullptr, m, n, b, d, &w, o.qr_tall == 1);
   if (!workspace || workspace_bytes < need) return QRCP_ERR_WORKSPACE;
-  carve_factor((char*)workspace, m, n, b, d, &w);
+  carve_factor((char*)workspace, m, n, b, d, &w, o.qr_tall == 1);
+  // columns the loop factors at most: min(m, n), or fewer in truncated mode
+  const i64 lim = o.max_rank > 0 ? std::min(std::min(m, n), (i64)o.max_rank) : std::min(m, n);
   hipStream_t st = (hipStream_t)stream;
   const Prec tprec = o.trailing_precision ? Prec::F32 : Prec::F64;
+  if (lim == 0) {
+    // no rows (m = 0): nothing to factor, J is the identity
+    QRCP_TRY(launch_iota(w.J[0], n, st));
+    QRCP_TRY(launch_jpiv_out(w.J[0], n, o.pivot_base, jpiv, st));
+    QRCP_HIP(hipStreamSynchronize(st));
+    return QRCP_OK;
+  }
 
   // ---- sketch M^sk = S A (S generated once, stored transposed) ----
   {
@@ -394,7 +444,8 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
   QRCP_TRY(zero_int(w.status, st));
 
   AuxStream* aux = nullptr;
-  QRCP_TRY(aux_stream(&aux));
+  if (getenv("QRCP_NO_LOOKAHEAD")) lookahead = false;
+  if (lookahead) QRCP_TRY(aux_stream(&aux));
   JoinGuard jg{st, aux};
   // the previous block's rank-k update of rows s+k .. m, started on the
   // second stream once the next block's pivots are known
@@ -407,7 +458,7 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
   auto start_pending = [&]() -> int {
     if (!pend.on) return QRCP_OK;
     pend.on = false;
-    if (getenv("QRCP_NO_LOOKAHEAD"))
+    if (!lookahead)
       return apply_qt_rows(w.Y, pend.r0, pend.r1, pend.k, m, pend.C, pend.nc, lda, tprec, w.W2, st);
     QRCP_HIP(hipEventRecord(aux->fork, st));
     QRCP_HIP(hipStreamWaitEvent(aux->s, aux->fork, 0));
@@ -423,38 +474,63 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
   // GETRF of the sketch (the selected columns are the same; the order of the
   // columns no block selects is not that of Alg. 2)
   const bool lu_all_steps = o.pivot_steps == 0;
-  for (i64 s = 0; s < n; ) {
+  for (i64 s = 0; s < lim; ) {
     const i64 ni = n - s, mi = m - s;
-    const int kmax = (int)std::min<i64>(b, std::min(ni, mi));
+    const int kmax = (int)std::min<i64>(std::min<i64>(b, lim - s), std::min(ni, mi));
     const i64 c = s + kmax;
+    // elimination steps of the sketch's GETRF: all min(d, n_i), bounded by
+    // m_i (the sketch of an m_i-row matrix has rank <= m_i: beyond it the
+    // Schur complement is zero in exact arithmetic, only a wide matrix's last
+    // blocks have m_i < min(d, n_i)); or the block's kmax with pivot_steps = 1
+    int lu_steps = 0;
+    if (!lu_all_steps) lu_steps = kmax;
+    else if (mi < std::min<i64>(d, ni)) lu_steps = (int)mi;
     double* Ablk = A + s + s * lda;  // panel top-left (rows s.., physical column s)
     // 1. pivots of the sketch (Alg. 2 GETRF on the transpose), all min(d, n_i)
     // elimination steps by default.  With pivot_steps = 1 only the first kmax
     // run: partial pivoting at step j depends on the steps before j alone, so
     // they fix the kmax selected columns, and the later steps only reorder the
     // columns this block leaves, which the next block selects among again.
-    {
-      ProfScope ps(kStLu, 2.0 * ni * d * (lu_all_steps ? std::min<i64>(d, ni) : kmax), st);
-      QRCP_TRY(launch_lu_pivots(w.sk0 + s * d, d, ni, d, w.xw, w.rec, w.rec_bytes, w.ipiv, w.jsk,
-                                w.status, st, lu_all_steps ? 0 : kmax));
-    }
-    // 2. logical maps and the placement plan; 3. permuted sketch
-    {
-      ProfScope ps(kStPerm, 0.0, st);
-      QRCP_TRY(launch_perm_plan(w.jsk, s, n, kmax, w.J[cur], w.J[1 - cur], w.phys[cur],
-                                w.phys[1 - cur], w.inv, w.plan, st));
-      QRCP_TRY(launch_sketch_permute(w.sk0 + s * d, w.sk1 + s * d, d, d, ni, w.jsk, st));
-    }
-    // The previous block's update runs beside the sketch QR and tri_rank
-    // (which touch only the sketch buffers), not beside the pivot selection,
-    // whose per-step exchange is slowed by the update's memory traffic.
-    QRCP_TRY(start_pending());
-    cur = 1 - cur;
-    // 4. R factor of the permuted sketch (back into sk0, logical positions)
-    {
-      ProfScope ps(kStSketchQr, 2.0 * d * d * ni, st);
-      QRCP_TRY(run_sketch_qr(w.sk1 + s * d, d, ni, d, w.sk0 + s * d, d, w.skqr, w.skqr_bytes,
-                             w.status, st));
+    if (o.qrcp_wide == 1) {
+      // column-pivoted QR of the sketch (GEQP3): pivots and R^sk in one pass,
+      // pivoting over the same rank bound as the LU (min(d, n_i, m_i) steps)
+      {
+        ProfScope ps(kStLu, 4.0 * d * d * ni, st);
+        QRCP_TRY(launch_sketch_geqp3(w.sk0 + s * d, d, ni, d, (int)std::min<i64>(std::min<i64>(d, ni), mi),
+                                     w.sk1 + s * d, w.sk0 + s * d, d, w.jsk, w.gq, w.gq_bytes,
+                                     w.status, st));
+      }
+      {
+        ProfScope ps(kStPerm, 0.0, st);
+        QRCP_TRY(launch_perm_plan(w.jsk, s, n, kmax, w.J[cur], w.J[1 - cur], w.phys[cur],
+                                  w.phys[1 - cur], w.inv, w.plan, st));
+      }
+      QRCP_TRY(start_pending());
+      cur = 1 - cur;
+    } else {
+      {
+        ProfScope ps(kStLu, 2.0 * ni * d * (lu_steps ? lu_steps : std::min<i64>(d, ni)), st);
+        QRCP_TRY(launch_lu_pivots(w.sk0 + s * d, d, ni, d, w.xw, w.rec, w.rec_bytes, w.ipiv, w.jsk,
+                                  w.status, st, lu_steps));
+      }
+      // 2. logical maps and the placement plan; 3. permuted sketch
+      {
+        ProfScope ps(kStPerm, 0.0, st);
+        QRCP_TRY(launch_perm_plan(w.jsk, s, n, kmax, w.J[cur], w.J[1 - cur], w.phys[cur],
+                                  w.phys[1 - cur], w.inv, w.plan, st));
+        QRCP_TRY(launch_sketch_permute(w.sk0 + s * d, w.sk1 + s * d, d, d, ni, w.jsk, st));
+      }
+      // The previous block's update runs beside the sketch QR and tri_rank
+      // (which touch only the sketch buffers), not beside the pivot selection,
+      // whose per-step exchange is slowed by the update's memory traffic.
+      QRCP_TRY(start_pending());
+      cur = 1 - cur;
+      // 4. R factor of the permuted sketch (back into sk0, logical positions)
+      {
+        ProfScope ps(kStSketchQr, 2.0 * d * d * ni, st);
+        QRCP_TRY(run_sketch_qr(w.sk1 + s * d, d, ni, d, w.sk0 + s * d, d, w.skqr, w.skqr_bytes,
+                               w.status, st));
+      }
     }
     const double* Rsk = w.sk0 + s * d;
     // 5. tri_rank
@@ -465,73 +541,102 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
       ProfScope ps(kStPerm, 0.0, st);
       QRCP_TRY(launch_place_columns(A, lda, m, s, kmax, w.plan, w.tmp, m, st));
     }
-    {
-      ProfScope ps(kStCholGram, 4.0 * mi * kmax * kmax, st);
-      // 7. precondition with the leading k x k block of Rsk (k on the device)
-      QRCP_TRY(launch_trinv_upper(Rsk, d, kmax, w.Rinv, b, st));
-      QRCP_TRY(launch_mask_k(w.Rinv, b, kmax, w.kdev, st));
-      QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, kmax, kmax, Ablk, lda, w.Rinv, b, w.Y, m),
-                    nullptr, 0, st));
-      // 8. Gram and Cholesky; a breakdown (or the rank cut) ends the factor at info
-      QRCP_TRY(gemm(true, false, Prec::F64, ga(kmax, kmax, (int)mi, w.Y, m, w.Y, m, w.G, b), w.split,
-                    kSplitBytes, st));
-      QRCP_TRY(launch_potrf_mw(w.G, b, kmax, w.info, w.split, kSplitBytes, st));
-    }
-    int hs[3];
-    QRCP_HIP(hipMemcpyAsync(hs, w.status, sizeof(int), hipMemcpyDeviceToHost, st));
-    QRCP_TRY(read_back(hs + 1, w.info, sizeof(int), st));
-    if (hs[0] != QRCP_OK) { status = hs[0]; ell = s; break; }
-    if (hs[1] < 0) { status = QRCP_ERR_TIMEOUT; ell = s; break; }
-    int k = hs[1];
-    if (k == 0) { ell = s; break; }
-    // Q = M^pre Rc^{-1}
-    {
-    ProfScope psq(kStCholQ, 2.0 * mi * k * k, st);
-    QRCP_TRY(launch_trinv_upper(w.G, b, k, w.Rinv, b, st));
-    if (o.cholqr_passes == 2) {
-      QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, k, k, w.Y, m, w.Rinv, b, w.tmp, m), nullptr, 0, st));
-      QRCP_TRY(gemm(true, false, Prec::F64, ga(k, k, (int)mi, w.tmp, m, w.tmp, m, w.R2, b), w.split, kSplitBytes, st));
-      QRCP_TRY(launch_potrf_mw(w.R2, b, k, w.info, w.split, kSplitBytes, st));
-      QRCP_TRY(read_back(hs + 2, w.info, sizeof(int), st));
-      if (hs[2] < 0) { status = QRCP_ERR_TIMEOUT; ell = s; break; }
-      if (hs[2] < k) {
-        // second pass broke down: keep the columns factored by both passes
-        k = hs[2];
-        if (k == 0) { ell = s; break; }
-        QRCP_TRY(launch_trinv_upper(w.G, b, k, w.Rinv, b, st));
-        QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, k, k, w.Y, m, w.Rinv, b, w.tmp, m), nullptr, 0, st));
+    int k = 0;
+    if (o.qr_tall == 1) {
+      // Householder QR of the panel (GEQRF; Sec. 2.3): the block rank from
+      // tri_rank sets the panel width, then 32-column leaves, each applied to
+      // the rest of the panel
+      int hs[2];
+      QRCP_HIP(hipMemcpyAsync(hs, w.status, sizeof(int), hipMemcpyDeviceToHost, st));
+      QRCP_TRY(read_back(hs + 1, w.kdev, sizeof(int), st));
+      if (hs[0] != QRCP_OK) { status = hs[0]; ell = s; break; }
+      k = hs[1];
+      if (k == 0) { ell = s; break; }
+      ProfScope ps(kStGeqrfPanel, 2.0 * mi * k * k - 2.0 * k * k * k / 3.0, st);
+      for (int s2 = 0; s2 < k; s2 += 32) {
+        const int ib = std::min(32, k - s2);
+        double* Al = Ablk + s2 + (i64)s2 * lda;
+        QRCP_TRY(launch_hh_leaf(Al, lda, mi - s2, ib, tau + s + s2, w.hrec, w.hrec_bytes, w.status, st));
+        if (s2 + ib < k) {
+          QRCP_TRY(launch_copy2d(Al, lda, w.tmp, m, mi - s2, ib, st));
+          QRCP_TRY(launch_unit_lower(Al, lda, ib, w.tmp, m, st));
+          QRCP_TRY(apply_qt_clean(w.tmp, mi - s2, ib, m, tau + s + s2, Al + (i64)ib * lda, k - s2 - ib,
+                                  lda, Prec::F64, w.G, w.Rc, b, w.W, w.W2, w.split, kSplitBytes, st));
+        }
       }
-      QRCP_TRY(launch_trinv_upper(w.R2, b, k, w.Uinv, b, st));
-      QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, k, k, w.tmp, m, w.Uinv, b, Ablk, lda), nullptr, 0, st));
-      // Rc <- R2 Rc
-      QRCP_TRY(gemm(false, false, Prec::F64, ga(k, k, k, w.R2, b, w.G, b, w.RcN, b), nullptr, 0, st));
-      QRCP_TRY(launch_copy2d(w.RcN, b, w.G, b, k, k, st));
+      // clean Y (unit lower trapezoidal) for the trailing update; R11 stays
+      // in place on and above the panel's diagonal
+      QRCP_TRY(launch_copy2d(Ablk, lda, w.Y, m, mi, k, st));
+      QRCP_TRY(launch_unit_lower(Ablk, lda, k, w.Y, m, st));
     } else {
-      QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, k, k, w.Y, m, w.Rinv, b, Ablk, lda), nullptr, 0, st));
-    }
-    }
-    // 9. Householder reconstruction: sign-modified LU of the head, Y2 = Q2 U^{-1}
-    {
-    ProfScope psr(kStRecon, 2.0 * (mi - k) * k * k + 2.0 * k * k * k, st);
-    QRCP_TRY(launch_headlu_mw(Ablk, lda, k, w.dsig, w.split, kSplitBytes, w.status, st));
-    QRCP_TRY(launch_tau_from_u(Ablk, lda, k, w.dsig, tau + s, st));
-    QRCP_TRY(launch_trinv_upper(Ablk, lda, k, w.Uinv, b, st));
-    if (mi > k) {
-      QRCP_TRY(gemm(false, false, Prec::F64, ga((int)(mi - k), k, k, Ablk + k, lda, w.Uinv, b, w.Y + k, m),
-                    nullptr, 0, st));
-      QRCP_TRY(launch_copy2d(w.Y + k, m, Ablk + k, lda, mi - k, k, st));
-    }
-    QRCP_TRY(launch_unit_lower(Ablk, lda, k, w.Y, m, st));
-    //    R11 = diag(D) Rc Rsk(0:k, 0:k)
-    QRCP_TRY(gemm(false, false, Prec::F64, ga(k, k, k, w.G, b, Rsk, d, w.P, b), nullptr, 0, st));
-    QRCP_TRY(launch_write_r11(w.P, b, k, w.dsig, Ablk, lda, st));
+      {
+        ProfScope ps(kStCholGram, 4.0 * mi * kmax * kmax, st);
+        // 7. precondition with the leading k x k block of Rsk (k on the device)
+        QRCP_TRY(launch_trinv_upper(Rsk, d, kmax, w.Rinv, b, st));
+        QRCP_TRY(launch_mask_k(w.Rinv, b, kmax, w.kdev, st));
+        QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, kmax, kmax, Ablk, lda, w.Rinv, b, w.Y, m),
+                      nullptr, 0, st));
+        // 8. Gram and Cholesky; a breakdown (or the rank cut) ends the factor at info
+        QRCP_TRY(gemm(true, false, Prec::F64, ga(kmax, kmax, (int)mi, w.Y, m, w.Y, m, w.G, b), w.split,
+                      kSplitBytes, st));
+        QRCP_TRY(launch_potrf_mw(w.G, b, kmax, w.info, w.split, kSplitBytes, st));
+      }
+      int hs[3];
+      QRCP_HIP(hipMemcpyAsync(hs, w.status, sizeof(int), hipMemcpyDeviceToHost, st));
+      QRCP_TRY(read_back(hs + 1, w.info, sizeof(int), st));
+      if (hs[0] != QRCP_OK) { status = hs[0]; ell = s; break; }
+      if (hs[1] < 0) { status = QRCP_ERR_TIMEOUT; ell = s; break; }
+      k = hs[1];
+      if (k == 0) { ell = s; break; }
+      // Q = M^pre Rc^{-1}
+      {
+      ProfScope psq(kStCholQ, 2.0 * mi * k * k, st);
+      QRCP_TRY(launch_trinv_upper(w.G, b, k, w.Rinv, b, st));
+      if (o.cholqr_passes == 2) {
+        QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, k, k, w.Y, m, w.Rinv, b, w.tmp, m), nullptr, 0, st));
+        QRCP_TRY(gemm(true, false, Prec::F64, ga(k, k, (int)mi, w.tmp, m, w.tmp, m, w.R2, b), w.split, kSplitBytes, st));
+        QRCP_TRY(launch_potrf_mw(w.R2, b, k, w.info, w.split, kSplitBytes, st));
+        QRCP_TRY(read_back(hs + 2, w.info, sizeof(int), st));
+        if (hs[2] < 0) { status = QRCP_ERR_TIMEOUT; ell = s; break; }
+        if (hs[2] < k) {
+          // second pass broke down: keep the columns factored by both passes
+          k = hs[2];
+          if (k == 0) { ell = s; break; }
+          QRCP_TRY(launch_trinv_upper(w.G, b, k, w.Rinv, b, st));
+          QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, k, k, w.Y, m, w.Rinv, b, w.tmp, m), nullptr, 0, st));
+        }
+        QRCP_TRY(launch_trinv_upper(w.R2, b, k, w.Uinv, b, st));
+        QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, k, k, w.tmp, m, w.Uinv, b, Ablk, lda), nullptr, 0, st));
+        // Rc <- R2 Rc
+        QRCP_TRY(gemm(false, false, Prec::F64, ga(k, k, k, w.R2, b, w.G, b, w.RcN, b), nullptr, 0, st));
+        QRCP_TRY(launch_copy2d(w.RcN, b, w.G, b, k, k, st));
+      } else {
+        QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, k, k, w.Y, m, w.Rinv, b, Ablk, lda), nullptr, 0, st));
+      }
+      }
+      // 9. Householder reconstruction: sign-modified LU of the head, Y2 = Q2 U^{-1}
+      {
+      ProfScope psr(kStRecon, 2.0 * (mi - k) * k * k + 2.0 * k * k * k, st);
+      QRCP_TRY(launch_headlu_mw(Ablk, lda, k, w.dsig, w.split, kSplitBytes, w.status, st));
+      QRCP_TRY(launch_tau_from_u(Ablk, lda, k, w.dsig, tau + s, st));
+      QRCP_TRY(launch_trinv_upper(Ablk, lda, k, w.Uinv, b, st));
+      if (mi > k) {
+        QRCP_TRY(gemm(false, false, Prec::F64, ga((int)(mi - k), k, k, Ablk + k, lda, w.Uinv, b, w.Y + k, m),
+                      nullptr, 0, st));
+        QRCP_TRY(launch_copy2d(w.Y + k, m, Ablk + k, lda, mi - k, k, st));
+      }
+      QRCP_TRY(launch_unit_lower(Ablk, lda, k, w.Y, m, st));
+      //    R11 = diag(D) Rc Rsk(0:k, 0:k)
+      QRCP_TRY(gemm(false, false, Prec::F64, ga(k, k, k, w.G, b, Rsk, d, w.P, b), nullptr, 0, st));
+      QRCP_TRY(launch_write_r11(w.P, b, k, w.dsig, Ablk, lda, st));
+      }
     }
     // 10-11. trailing update of the physical columns s+k .. n-1 (rows s..m-1)
     const i64 nc = n - s - k;
     double* Ct = A + s + (s + k) * lda;
     QRCP_TRY(apply_qt_w(w.Y, mi, k, m, tau + s, Ct, nc, lda, tprec, w.Tm, w.R11inv, b, w.W, w.W2,
                         w.split, kSplitBytes, st));
-    if (k < kmax || c >= n) {
+    if (k < kmax || c >= lim) {
       QRCP_TRY(apply_qt_rows(w.Y, 0, mi, k, m, Ct, nc, lda, tprec, w.W2, st));
       ell = s + k;
       break;
@@ -540,7 +645,7 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
     QRCP_TRY(apply_qt_rows(w.Y, 0, k, k, m, Ct, nc, lda, tprec, w.W2, st));
     // 12. sketch update: M^sk(0:b, c:) = Rsk12 - Rsk11 R11^{-1} R12 (R12 read through the map)
     ProfScope psu(kStSketchUpdate, 2.0 * b * b * (n - c), st);
-    if (o.cholqr_passes == 1) {
+    if (o.cholqr_passes == 1 && o.qr_tall == 0) {
       // R11 = diag(D) Rc Rsk11, so Rsk11 R11^{-1} = Rc^{-1} diag(D): the
       // inverse of the Cholesky factor is at hand (Q = M^pre Rc^{-1})
       QRCP_TRY(launch_scale_upper_cols(w.Rinv, b, w.dsig, (int)b, w.X, b, st));
@@ -580,34 +685,82 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
   return status;
 }
 
+}  // namespace
+}  // namespace qrcp
+
+extern "C" {
+
+int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size,
+                double sketch_factor, uint64_t seed, double tol, int64_t* jpiv, double* tau,
+                int64_t* rank, const qrcp_opts* opts, void* workspace, size_t workspace_bytes,
+                void* stream) {
+  return factor_impl(A, m, n, lda, block_size, sketch_factor, seed, tol, jpiv, tau, rank, opts,
+                     workspace, workspace_bytes, stream, true);
+}
+
+}  // extern "C"
+
 // ----------------------------------------------------------------------------
 // Unpivoted blocked Householder QR (GEQRF storage).
 // ----------------------------------------------------------------------------
-static size_t carve_geqrf(char* base, i64 m, i64 n, i64 nb, double** Yc, double** G, double** T,
-                          double** W, double** W2, uint64_t** rec, size_t* rec_bytes, int** status,
-                          double** split) {
+
+namespace qrcp {
+namespace {
+
+constexpr size_t kSplitBytesSmall = 32u << 20;  // split-K partials of the panel-side products
+
+struct GeqrfWs {
+  double* Yc[2];  // clean reflectors of the current and the previous panel
+  double* T[2];   // their compact WY factors
+  double *G, *Wn, *W2n;      // panel-side: Gram, next panel's W and W2
+  double *W, *W2;            // second stream: the rest of the trailing matrix
+  double *Yl, *Gl, *Tl, *Wl, *W2l;  // inside a panel: 32-column leaves
+  uint64_t* rec;
+  size_t rec_bytes;
+  int* status;
+  double *split, *split2;
+};
+
+size_t carve_geqrf(char* base, i64 m, i64 n, i64 nb, GeqrfWs* w) {
   Carver c{base};
-  *Yc = c.take<double>((size_t)m * nb);
-  *G = c.take<double>((size_t)nb * nb);
-  *T = c.take<double>((size_t)nb * nb);
-  *W = c.take<double>((size_t)nb * n);
-  *W2 = c.take<double>((size_t)nb * n);
-  *rec_bytes = hh_leaf_records_bytes(m);
-  *rec = c.take<uint64_t>(*rec_bytes / 8 + 1);
-  *status = c.take<int>(4);
-  *split = c.take<double>(kSplitBytes / 8);
+  for (int i = 0; i < 2; ++i) {
+    w->Yc[i] = c.take<double>((size_t)m * nb);
+    w->T[i] = c.take<double>((size_t)nb * nb);
+  }
+  w->G = c.take<double>((size_t)nb * nb);
+  w->Wn = c.take<double>((size_t)nb * nb);
+  w->W2n = c.take<double>((size_t)nb * nb);
+  w->W = c.take<double>((size_t)nb * n);
+  w->W2 = c.take<double>((size_t)nb * n);
+  w->Yl = c.take<double>((size_t)m * 32);
+  w->Gl = c.take<double>(32 * 32);
+  w->Tl = c.take<double>(32 * 32);
+  w->Wl = c.take<double>((size_t)32 * nb);
+  w->W2l = c.take<double>((size_t)32 * nb);
+  w->rec_bytes = hh_leaf_records_bytes(m);
+  w->rec = c.take<uint64_t>(w->rec_bytes / 8 + 1);
+  w->status = c.take<int>(4);
+  w->split = c.take<double>(kSplitBytes / 8);
+  w->split2 = c.take<double>(kSplitBytesSmall / 8);
   return c.off + kAlign;
 }
 
+}  // namespace
+}  // namespace qrcp
+
+extern "C" {
+
 size_t qrcp_geqrf_workspace_size(int64_t m, int64_t n, int64_t nb) {
   if (m < 0 || n < 0 || nb < 1) return 0;
-  double *a, *b, *c, *d, *e, *f;
-  uint64_t* r;
-  size_t rb;
-  int* s;
-  return carve_geqrf(nullptr, m, n, std::min<i64>(nb, std::max<i64>(n, 1)), &a, &b, &c, &d, &e, &r, &rb, &s, &f);
+  GeqrfWs w;
+  return carve_geqrf(nullptr, m, n, std::min<i64>(nb, std::max<i64>(n, 1)), &w);
 }
 
+// Blocked Householder QR with lookahead: after panel i is factored, the next
+// panel's columns are updated on the caller's stream and the rest of the
+// trailing matrix on the library's second stream, so the update of the far
+// columns runs beside the factorization of panel i+1 (joined before panel
+// i+1 updates panel i+2, whose columns that update writes).
 int qrcp_geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, int64_t nb,
                void* workspace, size_t workspace_bytes, void* stream) {
   if (m < 0) return -2;
@@ -620,40 +773,64 @@ int qrcp_geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, int64_
   if (!tau) return -5;
   if (m > 65536) return QRCP_ERR_UNSUPPORTED;
   nb = std::min<i64>(nb, n);
-  double *Yc, *G, *T, *W, *W2, *split;
-  uint64_t* rec;
-  size_t rec_bytes;
-  int* status;
-  const size_t need = carve_geqrf(nullptr, m, n, nb, &Yc, &G, &T, &W, &W2, &rec, &rec_bytes, &status, &split);
+  GeqrfWs w;
+  const size_t need = carve_geqrf(nullptr, m, n, nb, &w);
   if (!workspace || workspace_bytes < need) return QRCP_ERR_WORKSPACE;
-  carve_geqrf((char*)workspace, m, n, nb, &Yc, &G, &T, &W, &W2, &rec, &rec_bytes, &status, &split);
+  carve_geqrf((char*)workspace, m, n, nb, &w);
   hipStream_t st = (hipStream_t)stream;
-  QRCP_TRY(zero_int(status, st));
+  QRCP_TRY(zero_int(w.status, st));
+  AuxStream* aux = nullptr;
+  const bool lookahead = getenv("QRCP_NO_LOOKAHEAD") == nullptr;
+  if (lookahead) QRCP_TRY(aux_stream(&aux));
+  JoinGuard jg{st, aux};
   constexpr int IB = 32;
-  for (i64 s = 0; s < n; s += nb) {
+  int blk = 0;
+  for (i64 s = 0; s < n; s += nb, ++blk) {
     const i64 kb = std::min<i64>(nb, n - s), mi = m - s;
     double* Ap = A + s + s * lda;
-    for (i64 s2 = 0; s2 < kb; s2 += IB) {
-      const int ib = (int)std::min<i64>(IB, kb - s2);
-      double* Al = Ap + s2 + s2 * lda;
-      QRCP_TRY(launch_hh_leaf(Al, lda, mi - s2, ib, tau + s + s2, rec, rec_bytes, status, st));
-      if (s2 + ib < kb) {
-        // clean copy of the leaf's reflectors, then update the rest of the panel
-        QRCP_TRY(launch_copy2d(Al, lda, Yc, m, mi - s2, ib, st));
-        QRCP_TRY(launch_unit_lower(Al, lda, ib, Yc, m, st));
-        QRCP_TRY(apply_qt_clean(Yc, mi - s2, ib, m, tau + s + s2, Al + ib * lda, kb - s2 - ib, lda,
-                                Prec::F64, G, T, nb, W, W2, split, kSplitBytes, st));
+    {
+      ProfScope ps(kStGeqrfPanel, 2.0 * mi * kb * kb, st);
+      for (i64 s2 = 0; s2 < kb; s2 += IB) {
+        const int ib = (int)std::min<i64>(IB, kb - s2);
+        double* Al = Ap + s2 + s2 * lda;
+        QRCP_TRY(launch_hh_leaf(Al, lda, mi - s2, ib, tau + s + s2, w.rec, w.rec_bytes, w.status, st));
+        if (s2 + ib < kb) {
+          // clean copy of the leaf's reflectors, then update the rest of the panel
+          QRCP_TRY(launch_copy2d(Al, lda, w.Yl, m, mi - s2, ib, st));
+          QRCP_TRY(launch_unit_lower(Al, lda, ib, w.Yl, m, st));
+          QRCP_TRY(apply_qt_clean(w.Yl, mi - s2, ib, m, tau + s + s2, Al + ib * lda, kb - s2 - ib, lda,
+                                  Prec::F64, w.Gl, w.Tl, 32, w.Wl, w.W2l, w.split2, kSplitBytesSmall, st));
+        }
       }
     }
-    if (s + kb < n) {
-      QRCP_TRY(launch_copy2d(Ap, lda, Yc, m, mi, kb, st));
-      QRCP_TRY(launch_unit_lower(Ap, lda, (int)kb, Yc, m, st));
-      QRCP_TRY(apply_qt_clean(Yc, mi, (int)kb, m, tau + s, Ap + kb * lda, n - s - kb, lda, Prec::F64,
-                              G, T, nb, W, W2, split, kSplitBytes, st));
+    if (s + kb >= n) break;
+    double* Y = w.Yc[blk & 1];
+    double* T = w.T[blk & 1];
+    QRCP_TRY(launch_copy2d(Ap, lda, Y, m, mi, kb, st));
+    QRCP_TRY(launch_unit_lower(Ap, lda, (int)kb, Y, m, st));
+    QRCP_TRY(apply_qt_t(Y, mi, (int)kb, m, tau + s, w.G, T, nb, w.split2, kSplitBytesSmall, st));
+    // the next panel's columns: the previous block's far update wrote them
+    QRCP_TRY(jg.join());
+    const i64 nn = lookahead ? std::min<i64>(nb, n - s - kb) : n - s - kb;
+    double* Cn = Ap + kb * lda;
+    QRCP_TRY(apply_qt_wt(Y, mi, (int)kb, m, T, nb, Cn, nn, lda, Prec::F64, w.Wn, w.W2n, w.split2,
+                         kSplitBytesSmall, st));
+    QRCP_TRY(apply_qt_rows(Y, 0, mi, (int)kb, m, Cn, nn, lda, Prec::F64, w.W2n, st));
+    const i64 nf = n - s - kb - nn;
+    if (nf > 0) {
+      double* Cf = Ap + (kb + nn) * lda;
+      QRCP_HIP(hipEventRecord(aux->fork, st));
+      QRCP_HIP(hipStreamWaitEvent(aux->s, aux->fork, 0));
+      QRCP_TRY(apply_qt_wt(Y, mi, (int)kb, m, T, nb, Cf, nf, lda, Prec::F64, w.W, w.W2, w.split,
+                           kSplitBytes, aux->s));
+      QRCP_TRY(apply_qt_rows(Y, 0, mi, (int)kb, m, Cf, nf, lda, Prec::F64, w.W2, aux->s));
+      QRCP_HIP(hipEventRecord(aux->join, aux->s));
+      jg.pending = true;
     }
   }
+  QRCP_TRY(jg.join());
   int hs = 0;
-  QRCP_TRY(read_back(&hs, status, sizeof(int), st));
+  QRCP_TRY(read_back(&hs, w.status, sizeof(int), st));
   return hs;
 }
 

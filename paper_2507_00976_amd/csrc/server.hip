@@ -185,7 +185,6 @@ int qrcp_server_submit(qrcp_server* s, const qrcp_request* req, uint64_t* ticket
   if (r.m < 0 || r.n < 0 || r.lda < std::max<int64_t>(1, r.m) || r.block_size < 1 ||
       !(r.sketch_factor >= 1.0) || !(r.tol >= 0.0) || (!r.A && r.m * r.n > 0))
     return -2;
-  if (r.m < r.n) return QRCP_ERR_UNSUPPORTED;
   // the same up-front limits as qrcp_factor: sketch rows and the pivot
   // selection's resident grid for the first block
   if (r.n > 0 && (std::ceil(r.sketch_factor * (double)r.block_size - 1e-12) > 1024.0 ||

@@ -39,7 +39,9 @@ _i64, _u64, _i32, _u32, _dbl, _sz, _vp = (ctypes.c_int64, ctypes.c_uint64, ctype
 class QrcpOpts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("cholqr_passes", ctypes.c_int32),
                 ("sketch_precision", ctypes.c_int32), ("trailing_precision", ctypes.c_int32),
-                ("pivot_base", ctypes.c_int32), ("pivot_steps", ctypes.c_int32)]
+                ("pivot_base", ctypes.c_int32), ("pivot_steps", ctypes.c_int32),
+                ("qr_tall", ctypes.c_int32), ("qrcp_wide", ctypes.c_int32),
+                ("max_rank", ctypes.c_int64)]
 
 
 def _sig(name, res, *args):
@@ -108,7 +110,7 @@ _sig("qrcp_profile_read", ctypes.c_int, _i32, ctypes.POINTER(ctypes.c_double), c
      ctypes.POINTER(ctypes.c_double))
 
 EXPORTED = ["qrcp_profile_enable", "qrcp_profile_num_stages", "qrcp_profile_stage_name",
-            "qrcp_profile_read","qrcp_workspace_size", "qrcp_factor", "qrcp_geqrf_workspace_size", "qrcp_geqrf",
+            "qrcp_profile_read", "qrcp_workspace_size", "qrcp_factor", "qrcp_geqrf_workspace_size", "qrcp_geqrf",
             "qrcp_status_string", "qrcp_last_error", "qrcp_sketch_operator", "qrcp_philox",
             "qrcp_sketch", "qrcp_lu_workspace_size", "qrcp_lu_pivots",
             "qrcp_sketch_qr_workspace_size", "qrcp_sketch_qr", "qrcp_panel_workspace_size",
@@ -163,9 +165,9 @@ def _ws(nbytes: int, device) -> torch.Tensor:
 
 
 def _opts(cholqr_passes=1, sketch_precision=0, trailing_precision=0, pivot_base=0,
-          pivot_steps=0) -> QrcpOpts:
+          pivot_steps=0, qr_tall=0, qrcp_wide=0, max_rank=0) -> QrcpOpts:
     return QrcpOpts(ctypes.sizeof(QrcpOpts), cholqr_passes, sketch_precision, trailing_precision,
-                    pivot_base, pivot_steps)
+                    pivot_base, pivot_steps, qr_tall, qrcp_wide, max_rank)
 
 
 # ---------------------------------------------------------------- full method
@@ -175,12 +177,12 @@ def workspace_size(m, n, block_size, sketch_factor=1.25, **opts) -> int:
 
 
 def factor(A: torch.Tensor, block_size: int, sketch_factor: float = 1.25, seed: int = 42,
-           tol: float = 0.0, *, cholqr_passes: int = 1, sketch_precision: int = 0,
-           trailing_precision: int = 0, pivot_base: int = 0, pivot_steps: int = 0,
-           workspace: torch.Tensor | None = None, stream=None):
-    """qrcp_factor: A (m x n, column-major, overwritten) -> (A, jpiv, tau, rank)."""
+           tol: float = 0.0, *, workspace: torch.Tensor | None = None, stream=None, **opts):
+    """qrcp_factor: A (m x n, column-major, overwritten) -> (A, jpiv, tau, rank).
+    ``opts`` are qrcp_opts fields: cholqr_passes, sketch_precision,
+    trailing_precision, pivot_base, pivot_steps, qr_tall, qrcp_wide, max_rank."""
     ptr, m, n, lda = _cm(A, "A")
-    o = _opts(cholqr_passes, sketch_precision, trailing_precision, pivot_base, pivot_steps)
+    o = _opts(**opts)
     need = int(_lib.qrcp_workspace_size(m, n, block_size, sketch_factor, ctypes.byref(o)))
     if workspace is None:
         workspace = _ws(need, A.device)
@@ -350,9 +352,7 @@ class Server:
         self._live = {}
 
     def submit(self, A: torch.Tensor, block_size: int, sketch_factor: float = 1.25,
-               seed: int = 42, tol: float = 0.0, *, cholqr_passes: int = 1,
-               sketch_precision: int = 0, trailing_precision: int = 0,
-               pivot_base: int = 0, pivot_steps: int = 0) -> int:
+               seed: int = 42, tol: float = 0.0, **opts) -> int:
         ptr, m, n, lda = _cm(A, "A")
         jpiv = torch.empty(n, dtype=torch.int64, device=A.device)
         tau = torch.empty(min(m, n), dtype=torch.float64, device=A.device)
@@ -360,9 +360,7 @@ class Server:
         # before a server stream reads it
         torch.cuda.current_stream(A.device).synchronize()
         req = Request(ctypes.sizeof(Request), m, n, lda, block_size, sketch_factor, seed, tol,
-                      ptr, jpiv.data_ptr(), tau.data_ptr(),
-                      _opts(cholqr_passes, sketch_precision, trailing_precision, pivot_base,
-                            pivot_steps))
+                      ptr, jpiv.data_ptr(), tau.data_ptr(), _opts(**opts))
         t = _u64(0)
         _check(_lib.qrcp_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)),
                "qrcp_server_submit")

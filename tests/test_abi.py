@@ -57,14 +57,24 @@ def test_illegal_arguments_rejected_before_launch(lib):
     assert L.qrcp_factor(nul, 8, 4, 8, 2, 0.9, 1, 0.0, nul, nul, ctypes.byref(r), None, nul, 0, nul) == -6
     assert L.qrcp_factor(nul, 8, 4, 8, 2, 1.25, 1, -1.0, nul, nul, ctypes.byref(r), None, nul, 0, nul) == -8
     assert L.qrcp_factor(nul, 8, 4, 8, 2, 1.25, 1, 0.0, nul, nul, None, None, nul, 0, nul) == -11
-    # wide matrices are not supported; empty ones are a no-op
-    assert L.qrcp_factor(nul, 4, 8, 4, 2, 1.25, 1, 0.0, nul, nul, ctypes.byref(r), None, nul, 0, nul) == lib.QRCP_ERR_UNSUPPORTED
+    # wide matrices are checked like tall ones (A NULL is argument 1);
+    # empty ones are a no-op
+    assert L.qrcp_factor(nul, 4, 8, 4, 2, 1.25, 1, 0.0, nul, nul, ctypes.byref(r), None, nul, 0, nul) == -1
     assert L.qrcp_factor(nul, 4, 0, 4, 2, 1.25, 1, 0.0, nul, nul, ctypes.byref(r), None, nul, 0, nul) == 0
     # bad options
     o = lib.QrcpOpts(ctypes.sizeof(lib.QrcpOpts), 3, 0, 0, 0, 0)
     assert L.qrcp_factor(nul, 8, 4, 8, 2, 1.25, 1, 0.0, nul, nul, ctypes.byref(r), ctypes.byref(o), nul, 0, nul) == -12
     o = lib.QrcpOpts(ctypes.sizeof(lib.QrcpOpts), 1, 0, 0, 0, 2)
     assert L.qrcp_factor(nul, 8, 4, 8, 2, 1.25, 1, 0.0, nul, nul, ctypes.byref(r), ctypes.byref(o), nul, 0, nul) == -12
+    for bad in (lib._opts(qr_tall=2), lib._opts(qrcp_wide=5), lib._opts(max_rank=-1)):
+        assert L.qrcp_factor(nul, 8, 4, 8, 2, 1.25, 1, 0.0, nul, nul, ctypes.byref(r), ctypes.byref(bad),
+                             nul, 0, nul) == -12
+    # the Householder panel keeps one row per thread resident: m <= 65536
+    o = lib._opts(qr_tall=1)
+    assert L.qrcp_factor(fake16 := ctypes.c_void_p(16), 70000, 64, 70000, 32, 1.25, 1, 0.0, fake16, fake16,
+                         ctypes.byref(r), ctypes.byref(o), nul, 0, nul) == lib.QRCP_ERR_UNSUPPORTED
+    # the workspace grows by the leaf kernel's exchange records only
+    assert lib.workspace_size(4096, 512, 64, 1.25, qr_tall=1) > lib.workspace_size(4096, 512, 64, 1.25)
     # n above the pivot selection's resident grid (32768 columns) is refused
     # in the argument check, before any launch or workspace use
     fake = ctypes.c_void_p(16)
@@ -82,3 +92,4 @@ def test_illegal_arguments_rejected_before_launch(lib):
     assert L.qrcp_lu_pivots(nul, 0, 4, 4, nul, nul, nul, 0, nul) == -2
     assert L.qrcp_sketch_update(nul, 8, 9, 4, 8, nul, 8, nul, 8, nul, 0, nul) == -3
     assert L.qrcp_sketch_update_chol(nul, 8, 9, 4, 8, nul, 8, nul, nul, 8, nul, 0, nul) == -3
+

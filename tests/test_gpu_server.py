@@ -73,6 +73,25 @@ def test_server_small_budget_serializes():
 def test_server_rejects_unsupported():
     from paper_2507_00976_amd import qrcp
     with qrcp.Server(slots=1) as srv:
-        A = qrcp.colmajor(torch.zeros(8, 16, dtype=torch.float64, device="cuda"))
-        with pytest.raises(qrcp.QrcpError):
-            srv.submit(A, 4)
+        # a sketch of more than 1024 rows can never be admitted
+        A = qrcp.colmajor(torch.zeros(2048, 1000, dtype=torch.float64, device="cuda"))
+        with pytest.raises(qrcp.QrcpError) as e:
+            srv.submit(A, 900, 1.25)
+        assert e.value.code == qrcp.QRCP_ERR_UNSUPPORTED
+
+
+def test_server_wide_request_matches_alone():
+    """Wide requests (m < n) are admitted and give what a lone call gives."""
+    import numpy as np
+    import workloads as W
+    from paper_2507_00976_amd import qrcp
+    a = W.gaussian(96, 200, seed=41)
+    A1 = qrcp.colmajor(torch.from_numpy(a).cuda())
+    A1, j1, t1, r1 = qrcp.factor(A1, 32, 1.25, 3, 0.0)
+    with qrcp.Server(slots=2) as srv:
+        A2 = qrcp.colmajor(torch.from_numpy(a).cuda())
+        t = srv.submit(A2, 32, 1.25, 3, 0.0)
+        A2, j2, t2, r2, _ = srv.wait(t)
+    torch.cuda.synchronize()
+    assert r1 == r2 == 96
+    assert torch.equal(j1, j2) and torch.equal(A1, A2) and torch.equal(t1, t2)
