@@ -107,6 +107,26 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
                 int64_t* rank, const qrcp_opts* opts, void* workspace, size_t workspace_bytes,
                 void* stream);
 
+/*
+ * qrcp_factor without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts that
+ * forbid hipMalloc).  The workspace is a fixed device array inside the library
+ * (qrcp_noalloc_max_bytes() bytes, 192 MiB; each GPU that loads the library
+ * holds its own copy until the process ends); the call allocates nothing and
+ * creates no stream: every launch goes to `stream`, in qrcp_factor's order,
+ * with the same kernels, so the results equal qrcp_factor's bitwise.
+ * Arguments, outputs and errors as qrcp_factor; sizes whose
+ * qrcp_workspace_size() exceeds the array return QRCP_ERR_WORKSPACE before any
+ * launch (e.g. m = 4096, n = 1024, b = 64 needs 155 MiB and fits; 4096 x 4096
+ * at b = 256 does not).  All calls on one GPU share its array: calls that
+ * overlap in time on one GPU (two host threads, or two streams) race and give
+ * undefined results; serialize them.
+ */
+size_t qrcp_noalloc_max_bytes(void);
+int qrcp_factor_noalloc(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size,
+                        double sketch_factor, uint64_t seed, double tol, int64_t* jpiv,
+                        double* tau, int64_t* rank, const qrcp_opts* opts, void* stream);
+
 /* Unpivoted blocked Householder QR (GEQRF format), the performance baseline
  * the canonical FLOP rate is compared against (Sec. 1.4, Sec. 7).  A is m x n
  * DEVICE (m >= n), tau DEVICE min(m,n), nb = panel width. */

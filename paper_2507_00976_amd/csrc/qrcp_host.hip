@@ -378,7 +378,7 @@ size_t qrcp_workspace_size(int64_t m, int64_t n, int64_t block_size, double sket
 namespace qrcp {
 namespace {
 
-// The factorization behind qrcp_factor.  lookahead:
+// The factorization behind qrcp_factor and qrcp_factor_noalloc.  lookahead:
 // run the deferred rank-k update on the library's second stream (created on
 // first use); without it every launch goes to the caller's stream in the same
 // order, with the same arithmetic (the results are bitwise the same).
@@ -701,8 +701,73 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
 }  // extern "C"
 
 // ----------------------------------------------------------------------------
+// Allocation-free factorization: the workspace is a fixed device array of this
+// library, so the call needs no caller buffer and allocates nothing.
+// ----------------------------------------------------------------------------
+namespace qrcp {
+namespace {
+
+constexpr size_t kNoAllocBytes = size_t(192) << 20;
+
+// One copy per GPU (each device that loads the library holds its own until the
+// process ends).  Host code never passes this name to a kernel: it is only the
+// symbol looked up by hipGetSymbolAddress for the device-side address.
+__device__ __align__(256) char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+int scratch_address(void** out) {
+  int dev = 0;
+  QRCP_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return QRCP_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    QRCP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return QRCP_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return QRCP_OK;
+}
+
+}  // namespace
+}  // namespace qrcp
+
+extern "C" {
+
+size_t qrcp_noalloc_max_bytes(void) { return kNoAllocBytes; }
+
+int qrcp_factor_noalloc(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size,
+                        double sketch_factor, uint64_t seed, double tol, int64_t* jpiv,
+                        double* tau, int64_t* rank, const qrcp_opts* opts, void* stream) {
+  // qrcp_factor's own checks, all on the host before any launch: without a
+  // workspace the call ends at the workspace check if everything else holds
+  const int pre = factor_impl(A, m, n, lda, block_size, sketch_factor, seed, tol, jpiv, tau, rank,
+                              opts, nullptr, 0, stream, false);
+  if (pre != QRCP_ERR_WORKSPACE) return pre;
+  const size_t need = qrcp_workspace_size(m, n, block_size, sketch_factor, opts);
+  if (need > kNoAllocBytes) {
+    g_last_error = "qrcp_factor_noalloc: these sizes need " + std::to_string(need) +
+                   " bytes of workspace, above the fixed " + std::to_string(kNoAllocBytes) +
+                   "-byte device array";
+    return QRCP_ERR_WORKSPACE;
+  }
+  void* ws = nullptr;
+  QRCP_TRY(scratch_address(&ws));
+  // no second stream: the library creates nothing on this path
+  return factor_impl(A, m, n, lda, block_size, sketch_factor, seed, tol, jpiv, tau, rank, opts,
+                     ws, kNoAllocBytes, stream, false);
+}
+
+// ----------------------------------------------------------------------------
 // Unpivoted blocked Householder QR (GEQRF storage).
 // ----------------------------------------------------------------------------
+}  // extern "C"
 
 namespace qrcp {
 namespace {

@@ -54,6 +54,9 @@ def _sig(name, res, *args):
 _sig("qrcp_workspace_size", _sz, _i64, _i64, _i64, _dbl, ctypes.POINTER(QrcpOpts))
 _sig("qrcp_factor", ctypes.c_int, _vp, _i64, _i64, _i64, _i64, _dbl, _u64, _dbl, _vp, _vp,
      ctypes.POINTER(_i64), ctypes.POINTER(QrcpOpts), _vp, _sz, _vp)
+_sig("qrcp_noalloc_max_bytes", _sz)
+_sig("qrcp_factor_noalloc", ctypes.c_int, _vp, _i64, _i64, _i64, _i64, _dbl, _u64, _dbl, _vp, _vp,
+     ctypes.POINTER(_i64), ctypes.POINTER(QrcpOpts), _vp)
 _sig("qrcp_geqrf_workspace_size", _sz, _i64, _i64, _i64)
 _sig("qrcp_geqrf", ctypes.c_int, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _sz, _vp)
 _sig("qrcp_status_string", ctypes.c_char_p, ctypes.c_int)
@@ -110,7 +113,8 @@ _sig("qrcp_profile_read", ctypes.c_int, _i32, ctypes.POINTER(ctypes.c_double), c
      ctypes.POINTER(ctypes.c_double))
 
 EXPORTED = ["qrcp_profile_enable", "qrcp_profile_num_stages", "qrcp_profile_stage_name",
-            "qrcp_profile_read", "qrcp_workspace_size", "qrcp_factor", "qrcp_geqrf_workspace_size", "qrcp_geqrf",
+            "qrcp_profile_read", "qrcp_workspace_size", "qrcp_factor", "qrcp_noalloc_max_bytes",
+            "qrcp_factor_noalloc", "qrcp_geqrf_workspace_size", "qrcp_geqrf",
             "qrcp_status_string", "qrcp_last_error", "qrcp_sketch_operator", "qrcp_philox",
             "qrcp_sketch", "qrcp_lu_workspace_size", "qrcp_lu_pivots",
             "qrcp_sketch_qr_workspace_size", "qrcp_sketch_qr", "qrcp_panel_workspace_size",
@@ -193,6 +197,27 @@ def factor(A: torch.Tensor, block_size: int, sketch_factor: float = 1.25, seed: 
                           tau.data_ptr(), ctypes.byref(rank), ctypes.byref(o), workspace.data_ptr(),
                           workspace.numel(), _stream(stream))
     _check(rc, "qrcp_factor")
+    return A, jpiv, tau, int(rank.value)
+
+
+def noalloc_max_bytes() -> int:
+    return int(_lib.qrcp_noalloc_max_bytes())
+
+
+def factor_noalloc(A: torch.Tensor, block_size: int, sketch_factor: float = 1.25, seed: int = 42,
+                   tol: float = 0.0, *, jpiv: torch.Tensor, tau: torch.Tensor, stream=None, **opts):
+    """qrcp_factor_noalloc: as factor(), with the library's fixed device
+    workspace; the caller passes the jpiv (int64, n) and tau (float64,
+    min(m, n)) outputs.  Returns (A, jpiv, tau, rank)."""
+    ptr, m, n, lda = _cm(A, "A")
+    assert jpiv.is_cuda and jpiv.dtype == torch.int64 and jpiv.numel() >= n
+    assert tau.is_cuda and tau.dtype == torch.float64 and tau.numel() >= min(m, n)
+    o = _opts(**opts)
+    rank = _i64(0)
+    rc = _lib.qrcp_factor_noalloc(ptr, m, n, lda, block_size, sketch_factor, seed, tol,
+                                  jpiv.data_ptr(), tau.data_ptr(), ctypes.byref(rank),
+                                  ctypes.byref(o), _stream(stream))
+    _check(rc, "qrcp_factor_noalloc")
     return A, jpiv, tau, int(rank.value)
 
 

@@ -93,3 +93,24 @@ def test_illegal_arguments_rejected_before_launch(lib):
     assert L.qrcp_sketch_update(nul, 8, 9, 4, 8, nul, 8, nul, 8, nul, 0, nul) == -3
     assert L.qrcp_sketch_update_chol(nul, 8, 9, 4, 8, nul, 8, nul, nul, 8, nul, 0, nul) == -3
 
+
+def test_noalloc_checks_before_launch(lib):
+    """qrcp_factor_noalloc runs qrcp_factor's argument checks, then refuses
+    sizes beyond its fixed device array, all before any device work."""
+    L = lib._lib
+    r = ctypes.c_int64(0)
+    nul = None
+    assert lib.noalloc_max_bytes() == 192 << 20
+    assert L.qrcp_factor_noalloc(nul, -1, 4, 4, 2, 1.25, 1, 0.0, nul, nul, ctypes.byref(r), None, nul) == -2
+    assert L.qrcp_factor_noalloc(nul, 8, 4, 4, 2, 1.25, 1, 0.0, nul, nul, ctypes.byref(r), None, nul) == -4
+    assert L.qrcp_factor_noalloc(nul, 4, 8, 4, 2, 1.25, 1, 0.0, nul, nul, ctypes.byref(r), None,
+                                 nul) == -1
+    assert L.qrcp_factor_noalloc(nul, 0, 0, 1, 2, 1.25, 1, 0.0, nul, nul, ctypes.byref(r), None, nul) == 0
+    # 4096 x 4096 at b = 256 needs more than the array holds
+    assert lib.workspace_size(4096, 4096, 256, 1.25) > lib.noalloc_max_bytes()
+    p = ctypes.c_void_p(1 << 40)  # never dereferenced: the call stops at the size check
+    assert L.qrcp_factor_noalloc(p, 4096, 4096, 4096, 256, 1.25, 1, 0.0, p, p, ctypes.byref(r), None,
+                                 nul) == lib.QRCP_ERR_WORKSPACE
+    assert b"above the fixed" in L.qrcp_last_error()
+    # serving-sized problems fit
+    assert lib.workspace_size(4096, 1024, 64, 1.25) <= lib.noalloc_max_bytes()
