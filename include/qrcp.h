@@ -108,6 +108,31 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
                 void* stream);
 
 /*
+ * Stream-ordered form of qrcp_factor (Alg. 1): every block of the loop is
+ * enqueued on `stream` without reading anything back (the block's effective
+ * width and the stopping decision stay on the device; the launches of the
+ * blocks after the stop return at once), and the call returns before the
+ * work runs.  Results land in device memory once the stream reaches them:
+ * A, jpiv, tau as in qrcp_factor, and
+ *  rank_dev    DEVICE out, one int64: the detected rank l;
+ *  status_dev  DEVICE out, one int32: QRCP_OK or a QRCP_ERR_* code found on
+ *              the device (QRCP_ERR_NONFINITE, QRCP_ERR_TIMEOUT).
+ * The return value reports only what the host checks before any launch
+ * (illegal arguments -i, QRCP_ERR_UNSUPPORTED, QRCP_ERR_WORKSPACE,
+ * QRCP_ERR_HIP); argument numbering follows this signature (rank_dev = -11,
+ * status_dev = -12, opts = -13).  The caller keeps A, jpiv, tau, the two
+ * result words and the workspace alive until the stream has passed the call.
+ * The results equal qrcp_factor's bitwise (qrcp_factor is this call followed
+ * by one read-back).  Besides `stream` the call uses the library's second
+ * stream of the calling thread for the lookahead, joined into `stream`
+ * before the call's last launch.
+ */
+int qrcp_factor_async(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size,
+                      double sketch_factor, uint64_t seed, double tol, int64_t* jpiv, double* tau,
+                      int64_t* rank_dev, int32_t* status_dev, const qrcp_opts* opts,
+                      void* workspace, size_t workspace_bytes, void* stream);
+
+/*
  * qrcp_factor without a workspace argument, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, hosts that
  * forbid hipMalloc).  The workspace is a fixed device array inside the library

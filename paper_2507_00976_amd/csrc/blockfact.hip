@@ -109,8 +109,9 @@ __device__ __forceinline__ void atomic_min_agent(int* p, int v) {
 // -1 after a timeout.  One workgroup per upper block (bi <= bj).
 // flags: nb*nb slot flags + abort word, zero on entry; info: INT_MAX on entry.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(NT) void potrf_mw_kernel(double* G, long ldg, int n, int nb, int* info,
+__global__ __launch_bounds__(NT) void potrf_mw_kernel(Gate gt, double* G, long ldg, int n, int nb, int* info,
                                                       double* pub, int* flags) {
+  QRCP_GATE(gt);
   __shared__ double sBlk[BS][LDB];
   __shared__ double sP[BS][LDB];
   __shared__ double sQ[BS][LDB];
@@ -226,9 +227,10 @@ __global__ __launch_bounds__(NT) void potrf_mw_kernel(double* G, long ldg, int n
 // Slots: (p, j), j > p: U_pj; (i, p), i > p: L_ip; (p, p): U_pp^{-1};
 // nb*nb + p: L_pp^{-1}.  flags: nb*nb, zero on entry.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(NT) void headlu_mw_kernel(double* Q, long ldq, int k, int nb,
+__global__ __launch_bounds__(NT) void headlu_mw_kernel(Gate gt, double* Q, long ldq, int k, int nb,
                                                        double* dsig, double* pub, int* flags,
                                                        int* status) {
+  QRCP_GATE(gt);
   __shared__ double sBlk[BS][LDB];
   __shared__ double sP[BS][LDB];
   __shared__ double sQ[BS][LDB];
@@ -333,7 +335,8 @@ __global__ __launch_bounds__(NT) void headlu_mw_kernel(double* Q, long ldq, int 
   }
 }
 
-__global__ void mw_reset_kernel(int* flags, int nflags, int* info) {
+__global__ void mw_reset_kernel(Gate gt, int* flags, int nflags, int* info) {
+  QRCP_GATE(gt);
   for (int e = threadIdx.x; e < nflags; e += blockDim.x) flags[e] = 0;
   if (info && threadIdx.x == 0) *info = INT_MAX;
 }
@@ -364,11 +367,12 @@ int launch_potrf_mw(double* G, i64 ldg, int n, int* info_dev, void* scratch, siz
   const int nb = (n + BS - 1) / BS;
   double* pub = (double*)scratch;
   int* flags = (int*)((char*)scratch + (size_t)(kMaxNb * kMaxNb + kMaxNb) * SLOT * sizeof(double));
-  hipLaunchKernelGGL(mw_reset_kernel, dim3(1), dim3(256), 0, st, flags, nb * nb + 1, info_dev);
+  hipLaunchKernelGGL(mw_reset_kernel, dim3(1), dim3(256), 0, st, current_gate(), flags, nb * nb + 1, info_dev);
   QRCP_LAUNCHED("potrf reset");
   long ld = (long)ldg;
   int nbv = nb;
-  void* params[] = {&G, &ld, &n, &nbv, &info_dev, &pub, &flags};
+  Gate gt = current_gate();
+  void* params[] = {&gt, &G, &ld, &n, &nbv, &info_dev, &pub, &flags};
   return launch_resident((const void*)potrf_mw_kernel, dim3(nb * (nb + 1) / 2), dim3(NT), params, 0,
                          st);
 }
@@ -382,10 +386,11 @@ int launch_headlu_mw(double* Q, i64 ldq, int k, double* dsig, void* scratch, siz
   double* pub = (double*)scratch;
   int* flags = (int*)((char*)scratch + (size_t)(kMaxNb * kMaxNb + kMaxNb) * SLOT * sizeof(double));
   int* none = nullptr;
-  hipLaunchKernelGGL(mw_reset_kernel, dim3(1), dim3(256), 0, st, flags, nb * nb, none);
+  hipLaunchKernelGGL(mw_reset_kernel, dim3(1), dim3(256), 0, st, current_gate(), flags, nb * nb, none);
   QRCP_LAUNCHED("headlu reset");
   long ld = (long)ldq;
-  void* params[] = {&Q, &ld, &k, &nb, &dsig, &pub, &flags, &status};
+  Gate gt = current_gate();
+  void* params[] = {&gt, &Q, &ld, &k, &nb, &dsig, &pub, &flags, &status};
   return launch_resident((const void*)headlu_mw_kernel, dim3(nb * nb), dim3(NT), params, 0, st);
 }
 

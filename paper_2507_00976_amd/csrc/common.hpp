@@ -104,4 +104,64 @@ int launch_resident(const void* fn, dim3 grid, dim3 block, void** params, size_t
 // it turns a lost partner into QRCP_ERR_TIMEOUT instead of a hung GPU.
 constexpr long kSpinLimit = 1L << 22;
 
+// ---------------------------------------------------------------------------
+// Launch gates of the device-driven block loop.  The host enqueues every block
+// of the factorization up front; a control record in device memory says how
+// far the loop got, and every kernel of block `blk` returns at once when its
+// gate is closed:
+//   kGateRun   closed once the loop has stopped before block blk;
+//   kGateExit  open only in the block at which the loop stops (the work that
+//              finishes a block of reduced rank);
+//   kGateGoOn  open only in blocks the loop continues past (the sketch update).
+// The record is written by one-thread kernels earlier in the same stream, so
+// every kernel reads a settled value.  ctl == nullptr: always open.
+// ---------------------------------------------------------------------------
+struct LoopCtl {
+  int nblk;       // blocks that run (INT_MAX until the loop stops)
+  int exit_blk;   // the block at which the loop stops (-1 while it runs)
+  int k;          // effective width of the current block's panel
+  int status;     // QRCP_OK or the first error
+  long long ell;  // columns factored so far (the rank at the end)
+  long long perms;  // column-map updates done (parity selects the live map)
+};
+
+// rank and status of a factorization call, in device memory
+struct CallResult {
+  long long rank;
+  int status;
+  int pad;
+};
+
+enum : int { kGateRun = 0, kGateExit = 1, kGateGoOn = 2 };
+
+struct Gate {
+  const LoopCtl* ctl;
+  int blk;
+  int mode;
+};
+
+__device__ __forceinline__ bool gate_closed(const Gate& g) {
+  if (!g.ctl) return false;
+  const int nblk = g.ctl->nblk, ex = g.ctl->exit_blk;
+  if (g.blk >= nblk) return true;
+  if (g.mode == kGateExit) return g.blk != ex;
+  if (g.mode == kGateGoOn) return g.blk == ex;
+  return false;
+}
+
+#define QRCP_GATE(g)                        \
+  do {                                      \
+    if (::qrcp::gate_closed(g)) return;     \
+  } while (0)
+
+// The gate that launches on the calling host thread pass to their kernels
+// (open by default); set by the block loop.
+Gate& current_gate();
+
+struct GateScope {
+  Gate saved;
+  explicit GateScope(Gate g) : saved(current_gate()) { current_gate() = g; }
+  ~GateScope() { current_gate() = saved; }
+};
+
 }  // namespace qrcp

@@ -26,8 +26,9 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
   return c;
 }
 
-__global__ void philox_kernel(const uint32_t* ctr, long count, uint32_t k0, uint32_t k1,
+__global__ void philox_kernel(Gate gt, const uint32_t* ctr, long count, uint32_t k0, uint32_t k1,
                               uint32_t* out) {
+  QRCP_GATE(gt);
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (i >= count) return;
   uint4 c = make_uint4(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3]);
@@ -39,8 +40,9 @@ __global__ void philox_kernel(const uint32_t* ctr, long count, uint32_t k0, uint
 }
 
 // S^T (m x d, ld): S(2p, j), S(2p+1, j) from block (j, p, 0, 0) by Box-Muller.
-__global__ void sketch_operator_kernel(double* St, long m, int d, long ld, uint32_t k0,
+__global__ void sketch_operator_kernel(Gate gt, double* St, long m, int d, long ld, uint32_t k0,
                                        uint32_t k1) {
+  QRCP_GATE(gt);
   const long j = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const int p = blockIdx.y;
   if (j >= m) return;
@@ -58,7 +60,7 @@ __global__ void sketch_operator_kernel(double* St, long m, int d, long ld, uint3
 int launch_sketch_operator(double* St, i64 m, int d, i64 ldst, uint64_t seed, hipStream_t st) {
   if (m <= 0 || d <= 0) return QRCP_OK;
   dim3 grid((m + 255) / 256, (d + 1) / 2);
-  hipLaunchKernelGGL(sketch_operator_kernel, grid, dim3(256), 0, st, St, m, d, ldst,
+  hipLaunchKernelGGL(sketch_operator_kernel, grid, dim3(256), 0, st, current_gate(), St, m, d, ldst,
                      (uint32_t)seed, (uint32_t)(seed >> 32));
   QRCP_LAUNCHED("sketch_operator");
   return QRCP_OK;
@@ -67,7 +69,7 @@ int launch_sketch_operator(double* St, i64 m, int d, i64 ldst, uint64_t seed, hi
 int launch_philox(const uint32_t* ctr, i64 count, uint32_t k0, uint32_t k1, uint32_t* out,
                   hipStream_t st) {
   if (count <= 0) return QRCP_OK;
-  hipLaunchKernelGGL(philox_kernel, dim3((count + 255) / 256), dim3(256), 0, st, ctr, count, k0,
+  hipLaunchKernelGGL(philox_kernel, dim3((count + 255) / 256), dim3(256), 0, st, current_gate(), ctr, count, k0,
                      k1, out);
   QRCP_LAUNCHED("philox");
   return QRCP_OK;
@@ -78,7 +80,8 @@ int launch_philox(const uint32_t* ctr, i64 count, uint32_t k0, uint32_t k1, uint
 // strictly-upper(Y^T Y)).  A zero tau (H_j = I) decouples index j: its row and
 // column are cleared and T(j,j) = 0 afterwards.
 // ---------------------------------------------------------------------------
-__global__ void ut_prepare_kernel(double* G, long ldg, const double* tau, int n) {
+__global__ void ut_prepare_kernel(Gate gt, double* G, long ldg, const double* tau, int n) {
+  QRCP_GATE(gt);
   const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (idx >= (long)n * n) return;
   const int i = idx % n, j = idx / n;
@@ -88,21 +91,22 @@ __global__ void ut_prepare_kernel(double* G, long ldg, const double* tau, int n)
   if (i == j) *g = 1.0 / tau[i];
 }
 
-__global__ void ut_zero_diag_kernel(double* T, long ldt, const double* tau, int n) {
+__global__ void ut_zero_diag_kernel(Gate gt, double* T, long ldt, const double* tau, int n) {
+  QRCP_GATE(gt);
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < n && tau[j] == 0.0) T[j + (long)j * ldt] = 0.0;
 }
 
 int launch_ut_tinv(double* G, i64 ldg, const double* tau, int n, hipStream_t st) {
   if (n <= 0) return QRCP_OK;
-  hipLaunchKernelGGL(ut_prepare_kernel, dim3(((long)n * n + 255) / 256), dim3(256), 0, st, G, ldg,
+  hipLaunchKernelGGL(ut_prepare_kernel, dim3(((long)n * n + 255) / 256), dim3(256), 0, st, current_gate(), G, ldg,
                      tau, n);
   QRCP_LAUNCHED("ut_prepare");
   return QRCP_OK;
 }
 
 int launch_ut_zero_diag(double* T, i64 ldt, const double* tau, int n, hipStream_t st) {
-  hipLaunchKernelGGL(ut_zero_diag_kernel, dim3((n + 255) / 256), dim3(256), 0, st, T, ldt, tau, n);
+  hipLaunchKernelGGL(ut_zero_diag_kernel, dim3((n + 255) / 256), dim3(256), 0, st, current_gate(), T, ldt, tau, n);
   QRCP_LAUNCHED("ut_zero_diag");
   return QRCP_OK;
 }
@@ -233,8 +237,9 @@ __device__ __forceinline__ void tiled_mm(double* C, long ldc, int rows, int cols
 // on the FP64 matrix cores with the finished blocks of the column kept in LDS
 // (trinv_offdiag_kernel).  Orders above 512 use one wave per column.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void trinv_diag_kernel(const double* R, long ldr, int n,
+__global__ __launch_bounds__(256) void trinv_diag_kernel(Gate gt, const double* R, long ldr, int n,
                                                          double* X, long ldx) {
+  QRCP_GATE(gt);
   __shared__ double sR[W32][W32 + 1];
   const int tid = threadIdx.x, lane = tid & 63;
   const int p0 = blockIdx.x * W32, nb = min(W32, n - p0);
@@ -259,8 +264,9 @@ __global__ __launch_bounds__(256) void trinv_diag_kernel(const double* R, long l
 }
 
 template <int NBLK>
-__global__ __launch_bounds__(256) void trinv_offdiag_kernel(const double* R, long ldr, int n,
+__global__ __launch_bounds__(256) void trinv_offdiag_kernel(Gate gt, const double* R, long ldr, int n,
                                                             double* X, long ldx) {
+  QRCP_GATE(gt);
   __shared__ double sCol[NBLK][W32][W32 + 1];  // finished X_KJ of this column, [row][col]
   __shared__ double sS[W32][W32 + 1];
   __shared__ double sXd[W32][W32 + 1];
@@ -336,8 +342,9 @@ __global__ __launch_bounds__(256) void trinv_offdiag_kernel(const double* R, lon
 // LDS, so its workgroups find room on compute units shared with a concurrent
 // GEMM.  Operands are requested CH blocks at a time; the products run in the
 // same order as above (bitwise the same X).
-__global__ __launch_bounds__(256) void trinv_offdiag_gl_kernel(const double* R, long ldr, int n,
+__global__ __launch_bounds__(256) void trinv_offdiag_gl_kernel(Gate gt, const double* R, long ldr, int n,
                                                                double* X, long ldx) {
+  QRCP_GATE(gt);
   constexpr int CH = 3;
   __shared__ double sS[W32][W32 + 1];
   __shared__ double sXd[W32][W32 + 1];
@@ -401,8 +408,9 @@ __global__ __launch_bounds__(256) void trinv_offdiag_gl_kernel(const double* R, 
 }
 
 template <int NR>
-__global__ __launch_bounds__(256) void trinv_upper_kernel(const double* R, long ldr, int n,
+__global__ __launch_bounds__(256) void trinv_upper_kernel(Gate gt, const double* R, long ldr, int n,
                                                           double* X, long ldx) {
+  QRCP_GATE(gt);
   const int lane = threadIdx.x & 63;
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= n) return;
@@ -435,20 +443,20 @@ int launch_trinv_upper(const double* R, i64 ldr, int n, double* X, i64 ldx, hipS
   if (n <= 0) return QRCP_OK;
   if (n > 1024) return QRCP_ERR_UNSUPPORTED;
   if (n > 512) {
-    hipLaunchKernelGGL(trinv_upper_kernel<16>, dim3((n + 3) / 4), dim3(256), 0, st, R, ldr, n, X,
+    hipLaunchKernelGGL(trinv_upper_kernel<16>, dim3((n + 3) / 4), dim3(256), 0, st, current_gate(), R, ldr, n, X,
                        ldx);
     QRCP_LAUNCHED("trinv_upper");
     return QRCP_OK;
   }
   const int nblk = (n + W32 - 1) / W32;
-  hipLaunchKernelGGL(trinv_diag_kernel, dim3(nblk), dim3(256), 0, st, R, ldr, n, X, ldx);
+  hipLaunchKernelGGL(trinv_diag_kernel, dim3(nblk), dim3(256), 0, st, current_gate(), R, ldr, n, X, ldx);
   QRCP_LAUNCHED("trinv_diag");
   if (nblk > 1) {
     const dim3 g(nblk - 1), b(256);
-    if (low_lds) hipLaunchKernelGGL(trinv_offdiag_gl_kernel, g, b, 0, st, R, ldr, n, X, ldx);
-    else if (nblk <= 8) hipLaunchKernelGGL(trinv_offdiag_kernel<8>, g, b, 0, st, R, ldr, n, X, ldx);
-    else if (nblk <= 10) hipLaunchKernelGGL(trinv_offdiag_kernel<10>, g, b, 0, st, R, ldr, n, X, ldx);
-    else hipLaunchKernelGGL(trinv_offdiag_kernel<16>, g, b, 0, st, R, ldr, n, X, ldx);
+    if (low_lds) hipLaunchKernelGGL(trinv_offdiag_gl_kernel, g, b, 0, st, current_gate(), R, ldr, n, X, ldx);
+    else if (nblk <= 8) hipLaunchKernelGGL(trinv_offdiag_kernel<8>, g, b, 0, st, current_gate(), R, ldr, n, X, ldx);
+    else if (nblk <= 10) hipLaunchKernelGGL(trinv_offdiag_kernel<10>, g, b, 0, st, current_gate(), R, ldr, n, X, ldx);
+    else hipLaunchKernelGGL(trinv_offdiag_kernel<16>, g, b, 0, st, current_gate(), R, ldr, n, X, ldx);
     QRCP_LAUNCHED("trinv_offdiag");
   }
   return QRCP_OK;
@@ -462,7 +470,8 @@ int launch_trinv_upper(const double* R, i64 ldr, int n, double* X, i64 ldx, hipS
 // ---------------------------------------------------------------------------
 
 // Cholesky G = R^T R, upper.  *info = columns factored (n if no breakdown).
-__global__ __launch_bounds__(256) void potrf_upper_kernel(double* G, long ldg, int n, int* info) {
+__global__ __launch_bounds__(256) void potrf_upper_kernel(Gate gt, double* G, long ldg, int n, int* info) {
+  QRCP_GATE(gt);
   __shared__ double sD[SB][SB + 1];
   __shared__ double sX[SB][SB + 1];
   __shared__ double sA[SB][TTP];
@@ -522,7 +531,7 @@ __global__ __launch_bounds__(256) void potrf_upper_kernel(double* G, long ldg, i
 }
 
 int launch_potrf_upper(double* G, i64 ldg, int n, int* info_dev, hipStream_t st) {
-  hipLaunchKernelGGL(potrf_upper_kernel, dim3(1), dim3(256), 0, st, G, ldg, n, info_dev);
+  hipLaunchKernelGGL(potrf_upper_kernel, dim3(1), dim3(256), 0, st, current_gate(), G, ldg, n, info_dev);
   QRCP_LAUNCHED("potrf_upper");
   return QRCP_OK;
 }
@@ -530,7 +539,8 @@ int launch_potrf_upper(double* G, i64 ldg, int n, int* info_dev, hipStream_t st)
 // Sign-modified LU without pivoting of Q(0:k, 0:k) (Householder reconstruction):
 // at step j, D_j = -sgn(Q(j,j)) (sgn(0) = +1), Q(j,j) -= D_j, the column below
 // is divided by the new pivot and the trailing block updated.
-__global__ __launch_bounds__(256) void headlu_kernel(double* Q, long ldq, int k, double* dsig) {
+__global__ __launch_bounds__(256) void headlu_kernel(Gate gt, double* Q, long ldq, int k, double* dsig) {
+  QRCP_GATE(gt);
   __shared__ double sD[SB][SB + 1];
   __shared__ double sXu[SB][SB + 1];
   __shared__ double sXl[SB][SB + 1];
@@ -595,13 +605,14 @@ __global__ __launch_bounds__(256) void headlu_kernel(double* Q, long ldq, int k,
 
 int launch_headlu(double* Q, i64 ldq, int k, double* dsig, hipStream_t st) {
   if (k <= 0) return QRCP_OK;
-  hipLaunchKernelGGL(headlu_kernel, dim3(1), dim3(256), 0, st, Q, ldq, k, dsig);
+  hipLaunchKernelGGL(headlu_kernel, dim3(1), dim3(256), 0, st, current_gate(), Q, ldq, k, dsig);
   QRCP_LAUNCHED("headlu");
   return QRCP_OK;
 }
 
-__global__ void tau_from_u_kernel(const double* Q, long ldq, int k, const double* dsig,
+__global__ void tau_from_u_kernel(Gate gt, const double* Q, long ldq, int k, const double* dsig,
                                   double* tau) {
+  QRCP_GATE(gt);
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < k) tau[j] = -dsig[j] * Q[j + (long)j * ldq];
 }
@@ -609,14 +620,15 @@ __global__ void tau_from_u_kernel(const double* Q, long ldq, int k, const double
 int launch_tau_from_u(const double* Q, i64 ldq, int k, const double* dsig, double* tau,
                       hipStream_t st) {
   if (k <= 0) return QRCP_OK;
-  hipLaunchKernelGGL(tau_from_u_kernel, dim3((k + 255) / 256), dim3(256), 0, st, Q, ldq, k, dsig,
+  hipLaunchKernelGGL(tau_from_u_kernel, dim3((k + 255) / 256), dim3(256), 0, st, current_gate(), Q, ldq, k, dsig,
                      tau);
   QRCP_LAUNCHED("tau_from_u");
   return QRCP_OK;
 }
 
-__global__ void write_r11_kernel(const double* P, long ldp, int k, const double* dsig, double* A,
+__global__ void write_r11_kernel(Gate gt, const double* P, long ldp, int k, const double* dsig, double* A,
                                  long lda) {
+  QRCP_GATE(gt);
   const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (idx >= (long)k * k) return;
   const int i = idx % k, j = idx / k;
@@ -626,7 +638,7 @@ __global__ void write_r11_kernel(const double* P, long ldp, int k, const double*
 int launch_write_r11(const double* P, i64 ldp, int k, const double* dsig, double* A, i64 lda,
                      hipStream_t st) {
   if (k <= 0) return QRCP_OK;
-  hipLaunchKernelGGL(write_r11_kernel, dim3(((long)k * k + 255) / 256), dim3(256), 0, st, P, ldp,
+  hipLaunchKernelGGL(write_r11_kernel, dim3(((long)k * k + 255) / 256), dim3(256), 0, st, current_gate(), P, ldp,
                      k, dsig, A, lda);
   QRCP_LAUNCHED("write_r11");
   return QRCP_OK;
@@ -637,8 +649,9 @@ int launch_write_r11(const double* P, i64 ldp, int k, const double* dsig, double
 // ---------------------------------------------------------------------------
 // X = triu(S) diag(dvec) (n x n, column-major): the upper triangle of S with
 // column j scaled by dvec(j), zeros below the diagonal.
-__global__ void scale_upper_cols_kernel(const double* S, long lds, const double* dvec, int n,
+__global__ void scale_upper_cols_kernel(Gate gt, const double* S, long lds, const double* dvec, int n,
                                         double* X, long ldx) {
+  QRCP_GATE(gt);
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (e >= (long)n * n) return;
   const long i = e % n, j = e / n;
@@ -649,14 +662,15 @@ int launch_scale_upper_cols(const double* S, i64 lds, const double* dvec, int n,
                             i64 ldx, hipStream_t st) {
   if (n <= 0) return QRCP_OK;
   const long total = (long)n * n;
-  hipLaunchKernelGGL(scale_upper_cols_kernel, dim3((total + 255) / 256), dim3(256), 0, st, S,
+  hipLaunchKernelGGL(scale_upper_cols_kernel, dim3((total + 255) / 256), dim3(256), 0, st, current_gate(), S,
                      (long)lds, dvec, n, X, (long)ldx);
   QRCP_LAUNCHED("scale_upper_cols");
   return QRCP_OK;
 }
 
-__global__ void copy2d_kernel(const double* src, long lds, double* dst, long ldd, long rows,
+__global__ void copy2d_kernel(Gate gt, const double* src, long lds, double* dst, long ldd, long rows,
                               long cols, int mode) {
+  QRCP_GATE(gt);
   const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (idx >= rows * cols) return;
   const long i = idx % rows, j = idx / rows;
@@ -668,7 +682,7 @@ __global__ void copy2d_kernel(const double* src, long lds, double* dst, long ldd
 int launch_copy2d(const double* src, i64 lds, double* dst, i64 ldd, i64 rows, i64 cols,
                   hipStream_t st) {
   if (rows <= 0 || cols <= 0) return QRCP_OK;
-  hipLaunchKernelGGL(copy2d_kernel, dim3((rows * cols + 255) / 256), dim3(256), 0, st, src, lds,
+  hipLaunchKernelGGL(copy2d_kernel, dim3((rows * cols + 255) / 256), dim3(256), 0, st, current_gate(), src, lds,
                      dst, ldd, rows, cols, 0);
   QRCP_LAUNCHED("copy2d");
   return QRCP_OK;
@@ -677,13 +691,14 @@ int launch_copy2d(const double* src, i64 lds, double* dst, i64 ldd, i64 rows, i6
 int launch_triu_copy(const double* src, i64 lds, double* dst, i64 ldd, i64 rows, i64 cols,
                      hipStream_t st) {
   if (rows <= 0 || cols <= 0) return QRCP_OK;
-  hipLaunchKernelGGL(copy2d_kernel, dim3((rows * cols + 255) / 256), dim3(256), 0, st, src, lds,
+  hipLaunchKernelGGL(copy2d_kernel, dim3((rows * cols + 255) / 256), dim3(256), 0, st, current_gate(), src, lds,
                      dst, ldd, rows, cols, 1);
   QRCP_LAUNCHED("triu_copy");
   return QRCP_OK;
 }
 
-__global__ void fill_kernel(double* dst, long ld, long rows, long cols, double v) {
+__global__ void fill_kernel(Gate gt, double* dst, long ld, long rows, long cols, double v) {
+  QRCP_GATE(gt);
   const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (idx >= rows * cols) return;
   dst[idx % rows + (idx / rows) * ld] = v;
@@ -691,38 +706,41 @@ __global__ void fill_kernel(double* dst, long ld, long rows, long cols, double v
 
 int launch_fill(double* dst, i64 ld, i64 rows, i64 cols, double v, hipStream_t st) {
   if (rows <= 0 || cols <= 0) return QRCP_OK;
-  hipLaunchKernelGGL(fill_kernel, dim3((rows * cols + 255) / 256), dim3(256), 0, st, dst, ld, rows,
+  hipLaunchKernelGGL(fill_kernel, dim3((rows * cols + 255) / 256), dim3(256), 0, st, current_gate(), dst, ld, rows,
                      cols, v);
   QRCP_LAUNCHED("fill");
   return QRCP_OK;
 }
 
-__global__ void fill_u64_kernel(uint64_t* dst, long count, uint64_t v) {
+__global__ void fill_u64_kernel(Gate gt, uint64_t* dst, long count, uint64_t v) {
+  QRCP_GATE(gt);
   const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (idx < count) dst[idx] = v;
 }
 
 int launch_fill_u64(uint64_t* dst, i64 count, uint64_t v, hipStream_t st) {
   if (count <= 0) return QRCP_OK;
-  hipLaunchKernelGGL(fill_u64_kernel, dim3((count + 255) / 256), dim3(256), 0, st, dst, count, v);
+  hipLaunchKernelGGL(fill_u64_kernel, dim3((count + 255) / 256), dim3(256), 0, st, current_gate(), dst, count, v);
   QRCP_LAUNCHED("fill_u64");
   return QRCP_OK;
 }
 
 // identity diagonal: dst(i,i) = 1 for a square n x n already zero-filled
-__global__ void set_diag_kernel(double* dst, long ld, long n, double v) {
+__global__ void set_diag_kernel(Gate gt, double* dst, long ld, long n, double v) {
+  QRCP_GATE(gt);
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (i < n) dst[i + i * ld] = v;
 }
 
 int launch_set_identity(double* dst, i64 ld, i64 n, hipStream_t st) {
   QRCP_TRY(launch_fill(dst, ld, n, n, 0.0, st));
-  hipLaunchKernelGGL(set_diag_kernel, dim3((n + 255) / 256), dim3(256), 0, st, dst, ld, n, 1.0);
+  hipLaunchKernelGGL(set_diag_kernel, dim3((n + 255) / 256), dim3(256), 0, st, current_gate(), dst, ld, n, 1.0);
   QRCP_LAUNCHED("set_diag");
   return QRCP_OK;
 }
 
-__global__ void any_nonfinite_kernel(const double* X, long ld, long rows, long cols, int* flag) {
+__global__ void any_nonfinite_kernel(Gate gt, const double* X, long ld, long rows, long cols, int* flag) {
+  QRCP_GATE(gt);
   const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
   bool bad = false;
   if (idx < rows * cols) bad = !isfinite(X[idx % rows + (idx / rows) * ld]);
@@ -731,7 +749,7 @@ __global__ void any_nonfinite_kernel(const double* X, long ld, long rows, long c
 
 int launch_any_nonfinite(const double* X, i64 ld, i64 rows, i64 cols, int* flag, hipStream_t st) {
   if (rows <= 0 || cols <= 0) return QRCP_OK;
-  hipLaunchKernelGGL(any_nonfinite_kernel, dim3((rows * cols + 255) / 256), dim3(256), 0, st, X,
+  hipLaunchKernelGGL(any_nonfinite_kernel, dim3((rows * cols + 255) / 256), dim3(256), 0, st, current_gate(), X,
                      ld, rows, cols, flag);
   QRCP_LAUNCHED("any_nonfinite");
   return QRCP_OK;

@@ -407,7 +407,8 @@ __device__ __forceinline__ void gemm_vec_body(const GemmArgs& g) {
 // their own kernel symbols so that profiles attribute time to them.
 #define QRCP_GEMM_KERNEL(NAME)                                                              \
   template <int BM, int BN, int WGM, int WGN, int BK, bool TA, bool TB, typename T, bool VEC> \
-  __global__ __launch_bounds__(64 * WGM * WGN) void NAME(GemmArgs g) {                        \
+  __global__ __launch_bounds__(64 * WGM * WGN) void NAME(Gate gt, GemmArgs g) {               \
+    QRCP_GATE(gt);                                                                             \
     if constexpr (VEC) gemm_vec_body<BM, BN, WGM, WGN, BK, TA, TB>(g);                        \
     else gemm_body<BM, BN, WGM, WGN, BK, TA, TB, T>(g);                                       \
   }
@@ -419,7 +420,8 @@ QRCP_GEMM_KERNEL(sketch_gemm_kernel)
 
 // BF16 x BF16 -> FP32 sketch kernel: op(A) = S (from S^T stored K x M, TA),
 // op(B) = the FP64 matrix (K x N).  BK = 32, two k-steps of 16 per chunk.
-__global__ __launch_bounds__(256) void gemm_bf16_tn_kernel(GemmArgs g) {
+__global__ __launch_bounds__(256) void gemm_bf16_tn_kernel(Gate gt, GemmArgs g) {
+  QRCP_GATE(gt);
   constexpr int BM = 64, BN = 64, BK = 32;
   constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
   __shared__ unsigned short sA[BM][BK + 4];
@@ -491,8 +493,9 @@ __global__ __launch_bounds__(256) void gemm_bf16_tn_kernel(GemmArgs g) {
 // Fixed-order reduction of split-K partials: C = alpha * sum_z P_z + beta * C.
 // For the BF16 path (fp32_sum) the partials are summed in FP32 so the whole
 // accumulation stays FP32.
-__global__ void splitk_reduce_kernel(const double* P, int splits, int M, int N, double alpha,
+__global__ void splitk_reduce_kernel(Gate gt, const double* P, int splits, int M, int N, double alpha,
                                      double beta, double* C, long ldc, int fp32_sum) {
+  QRCP_GATE(gt);
   const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long MN = (long)M * N;
   if (idx >= MN) return;
@@ -511,7 +514,8 @@ __global__ void splitk_reduce_kernel(const double* P, int splits, int M, int N, 
   *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
 }
 
-__global__ void scale_kernel(double* C, long ldc, int M, int N, double beta) {
+__global__ void scale_kernel(Gate gt, double* C, long ldc, int M, int N, double beta) {
+  QRCP_GATE(gt);
   const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (idx >= (long)M * N) return;
   double* c = C + idx % M + (idx / M) * ldc;
@@ -524,16 +528,16 @@ static void launch_tile(const GemmArgs& g, int splits, hipStream_t st) {
   dim3 block(64 * WGM * WGN);
   switch (g.kind) {
     case GemmKind::TrailingUpdate:
-      hipLaunchKernelGGL((trailing_update_kernel<BM, BN, WGM, WGN, BK, TA, TB, T, VEC>), grid, block, 0, st, g);
+      hipLaunchKernelGGL((trailing_update_kernel<BM, BN, WGM, WGN, BK, TA, TB, T, VEC>), grid, block, 0, st, current_gate(), g);
       break;
     case GemmKind::TrailingW:
-      hipLaunchKernelGGL((trailing_w_kernel<BM, BN, WGM, WGN, BK, TA, TB, T, VEC>), grid, block, 0, st, g);
+      hipLaunchKernelGGL((trailing_w_kernel<BM, BN, WGM, WGN, BK, TA, TB, T, VEC>), grid, block, 0, st, current_gate(), g);
       break;
     case GemmKind::Sketch:
-      hipLaunchKernelGGL((sketch_gemm_kernel<BM, BN, WGM, WGN, BK, TA, TB, T, VEC>), grid, block, 0, st, g);
+      hipLaunchKernelGGL((sketch_gemm_kernel<BM, BN, WGM, WGN, BK, TA, TB, T, VEC>), grid, block, 0, st, current_gate(), g);
       break;
     default:
-      hipLaunchKernelGGL((gemm_kernel<BM, BN, WGM, WGN, BK, TA, TB, T, VEC>), grid, block, 0, st, g);
+      hipLaunchKernelGGL((gemm_kernel<BM, BN, WGM, WGN, BK, TA, TB, T, VEC>), grid, block, 0, st, current_gate(), g);
   }
 }
 
@@ -618,7 +622,7 @@ int gemm(bool ta, bool tb, Prec prec, GemmArgs g, double* split_ws, size_t split
   if (g.K <= 0) {
     // empty product: C = beta * C
     if (g.beta == 1.0) return QRCP_OK;
-    hipLaunchKernelGGL(scale_kernel, dim3((g.M * (long)g.N + 255) / 256), dim3(256), 0, st, g.C,
+    hipLaunchKernelGGL(scale_kernel, dim3((g.M * (long)g.N + 255) / 256), dim3(256), 0, st, current_gate(), g.C,
                        g.ldc, g.M, g.N, g.beta);
     QRCP_LAUNCHED("gemm scale");
     return QRCP_OK;
@@ -641,7 +645,7 @@ int gemm(bool ta, bool tb, Prec prec, GemmArgs g, double* split_ws, size_t split
     if (!ta || tb) return QRCP_ERR_UNSUPPORTED;
     dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, splits);
     if (splits == 1) g.partial = nullptr;
-    hipLaunchKernelGGL(gemm_bf16_tn_kernel, grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL(gemm_bf16_tn_kernel, grid, dim3(256), 0, st, current_gate(), g);
   } else if (prec == Prec::F32) {
     if (ta && !tb) launch_shape<true, false, float>(g, splits, st);
     else if (!ta && !tb) launch_shape<false, false, float>(g, splits, st);
@@ -656,7 +660,7 @@ int gemm(bool ta, bool tb, Prec prec, GemmArgs g, double* split_ws, size_t split
   QRCP_LAUNCHED("gemm");
   if (splits > 1) {
     const long MN = (long)g.M * g.N;
-    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((MN + 255) / 256), dim3(256), 0, st, split_ws,
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((MN + 255) / 256), dim3(256), 0, st, current_gate(), split_ws,
                        splits, g.M, g.N, alpha, beta, C, ldc, prec != Prec::F64 ? 1 : 0);
     QRCP_LAUNCHED("splitk_reduce");
   }

@@ -34,10 +34,11 @@ __device__ __forceinline__ bool beats(double va, long ia, double vb, long ib) {
   return ib < 0 || (ia >= 0 && (va > vb || (va == vb && ia < ib)));
 }
 
-__global__ __launch_bounds__(NT) void geqp3_update_kernel(double* X, long ld, int d, long ni,
+__global__ __launch_bounds__(NT) void geqp3_update_kernel(Gate gt, double* X, long ld, int d, long ni,
                                                           int refl, const double* tau, long c0,
                                                           double* part_v, long* part_i,
                                                           int* status) {
+  QRCP_GATE(gt);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long nw = (long)gridDim.x * kWavesPerGroup;
   const int r0 = refl + 1;  // the norms are over rows r0 .. d-1
@@ -95,9 +96,10 @@ __global__ __launch_bounds__(NT) void geqp3_update_kernel(double* X, long ld, in
   }
 }
 
-__global__ __launch_bounds__(NT) void geqp3_pivot_kernel(double* X, long ld, int d, int j, int pivot,
+__global__ __launch_bounds__(NT) void geqp3_pivot_kernel(Gate gt, double* X, long ld, int d, int j, int pivot,
                                                          const double* part_v, const long* part_i,
                                                          int nparts, i64* jsk, double* tau) {
+  QRCP_GATE(gt);
   __shared__ double sv[NT];
   __shared__ long si[NT];
   __shared__ double red[NT / 64];
@@ -181,17 +183,17 @@ int launch_sketch_geqp3(const double* Msk, int d, i64 ni, i64 ld, int psteps, do
   const int steps = (int)std::min<i64>(d, ni);
   // norms of all columns over all rows, for the first pivot
   int parts = parts_for(ni);
-  hipLaunchKernelGGL(geqp3_update_kernel, dim3(parts), dim3(NT), 0, st, X, (long)d, d, (long)ni, -1,
+  hipLaunchKernelGGL(geqp3_update_kernel, dim3(parts), dim3(NT), 0, st, current_gate(), X, (long)d, d, (long)ni, -1,
                      (const double*)tau, 0L, part_v, part_i, status);
   QRCP_LAUNCHED("geqp3_update");
   for (int j = 0; j < steps; ++j) {
-    hipLaunchKernelGGL(geqp3_pivot_kernel, dim3(1), dim3(NT), 0, st, X, (long)d, d, j,
+    hipLaunchKernelGGL(geqp3_pivot_kernel, dim3(1), dim3(NT), 0, st, current_gate(), X, (long)d, d, j,
                        j < psteps ? 1 : 0, (const double*)part_v, (const long*)part_i, parts, jsk,
                        tau);
     QRCP_LAUNCHED("geqp3_pivot");
     if (j + 1 < ni) {
       parts = parts_for(ni - j - 1);
-      hipLaunchKernelGGL(geqp3_update_kernel, dim3(parts), dim3(NT), 0, st, X, (long)d, d,
+      hipLaunchKernelGGL(geqp3_update_kernel, dim3(parts), dim3(NT), 0, st, current_gate(), X, (long)d, d,
                          (long)ni, j, (const double*)tau, (long)(j + 1), part_v, part_i, status);
       QRCP_LAUNCHED("geqp3_update");
     }

@@ -42,7 +42,8 @@ __device__ __forceinline__ uint64_t poll_w(uint64_t* p, bool& to) {
   return v;
 }
 
-__global__ __launch_bounds__(NT) void hh_leaf_kernel(LeafArgs a) {
+__global__ __launch_bounds__(NT) void hh_leaf_kernel(Gate gt, LeafArgs a) {
+  QRCP_GATE(gt);
   __shared__ double sRed[NT / 64][64][IB + 1];  // per-wave rows -> reduced per wave below
   __shared__ double sSum[8][IB];
   __shared__ double sAll[8][IB];
@@ -168,7 +169,8 @@ int launch_hh_leaf(double* A, i64 lda, i64 mi, int ib, double* tau, uint64_t* re
   if (need > rec_bytes) return QRCP_ERR_WORKSPACE;
   QRCP_TRY(launch_fill_u64(rec, (i64)(need / 8), SENT, st));
   LeafArgs args{A, (long)lda, (long)mi, ib, tau, rec, status};
-  void* params[] = {&args};
+  Gate gt = current_gate();
+  void* params[] = {&gt, &args};
   QRCP_TRY(launch_resident((const void*)hh_leaf_kernel, dim3(G), dim3(NT), params, 0, st));
   return QRCP_OK;
 }

@@ -198,7 +198,8 @@ __device__ __forceinline__ void lu_forward_subst(double (&u)[NB], const double (
 }
 
 template <int RPT>
-__global__ __launch_bounds__(NT) void lu_pivots_kernel(LuArgs a) {
+__global__ __launch_bounds__(NT) void lu_pivots_kernel(Gate gt, LuArgs a) {
+  QRCP_GATE(gt);
   constexpr int R = 64 * RPT;
   // row strides padded so that the matrix-core operand reads are free of bank conflicts
   // Panel state is double-buffered by panel parity: waves 1-3 update the
@@ -702,7 +703,8 @@ int launch_lu_pivots(const double* Msk, int d, i64 ni, i64 ld, double* Xw, uint6
   if (max_steps > 0) steps = std::min(steps, max_steps);
   QRCP_TRY(launch_fill_u64(rec, (i64)(need / sizeof(uint64_t)), SENT, st));
   LuArgs args{Msk, (long)ld, d, (long)ni, steps, Xw, rec, (long*)ipiv, (long*)jsk, status_dev};
-  void* params[] = {&args};
+  Gate gt = current_gate();
+  void* params[] = {&gt, &args};
   const void* fn = rpt == 1 ? (const void*)lu_pivots_kernel<1> : (const void*)lu_pivots_kernel<2>;
   QRCP_TRY(launch_resident(fn, dim3(G), dim3(NT), params, 0, st));
   return QRCP_OK;

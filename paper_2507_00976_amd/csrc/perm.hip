@@ -17,10 +17,11 @@ namespace qrcp {
 
 // plan layout: plan[0] = nD; plan[8 + t] = source column of panel slot t;
 // plan[8 + kmax + q] = displaced slot D[q]; plan[8 + 2 kmax + q] = free slot F[q].
-__global__ __launch_bounds__(1024) void perm_plan_kernel(const long* jsk, long s, long n, int kmax,
+__global__ __launch_bounds__(1024) void perm_plan_kernel(Gate gt, const long* jsk, long s, long n, int kmax,
                                                         const long* J0, long* J1,
                                                         const long* phys0, long* phys1, long* inv,
                                                         long* plan) {
+  QRCP_GATE(gt);
   extern __shared__ long sm[];
   long* src = sm;              // kmax: physical column of panel slot t
   long* dsl = src + kmax;      // kmax: displaced slots, in increasing order
@@ -98,13 +99,15 @@ __global__ __launch_bounds__(1024) void perm_plan_kernel(const long* jsk, long s
     phys1[s + t] = s + t;
     inv[s + t] = s + t;
   }
+  // one more map update: the live maps alternate between the two buffers
+  if (tid == 0 && gt.ctl) const_cast<LoopCtl*>(gt.ctl)->perms += 1;
 }
 
 int launch_perm_plan(const i64* jsk, i64 s, i64 n, int kmax, const i64* J0, i64* J1,
                      const i64* phys0, i64* phys1, i64* inv, i64* plan, hipStream_t st) {
   const size_t smem = (size_t)kmax * 8 * 3 + (size_t)kmax * 4 + 16;
   if (smem > 64 * 1024) return QRCP_ERR_UNSUPPORTED;
-  hipLaunchKernelGGL(perm_plan_kernel, dim3(1), dim3(1024), smem, st, (const long*)jsk, s, n, kmax,
+  hipLaunchKernelGGL(perm_plan_kernel, dim3(1), dim3(1024), smem, st, current_gate(), (const long*)jsk, s, n, kmax,
                      (const long*)J0, (long*)J1, (const long*)phys0, (long*)phys1, (long*)inv,
                      (long*)plan);
   QRCP_LAUNCHED("perm_plan");
@@ -112,8 +115,9 @@ int launch_perm_plan(const i64* jsk, i64 s, i64 n, int kmax, const i64* J0, i64*
 }
 
 // dst(:, t) = src(:, jsk[t]) for t < ni (d rows, same leading dimension)
-__global__ void sketch_permute_kernel(const double* src, double* dst, int d, long ld, long ni,
+__global__ void sketch_permute_kernel(Gate gt, const double* src, double* dst, int d, long ld, long ni,
                                       const long* jsk) {
+  QRCP_GATE(gt);
   const long t = blockIdx.x;
   if (t >= ni) return;
   const double* a = src + jsk[t] * ld;
@@ -124,22 +128,24 @@ __global__ void sketch_permute_kernel(const double* src, double* dst, int d, lon
 int launch_sketch_permute(const double* src, double* dst, int d, i64 ld, i64 ni, const i64* jsk,
                           hipStream_t st) {
   if (ni <= 0) return QRCP_OK;
-  hipLaunchKernelGGL(sketch_permute_kernel, dim3(ni), dim3(128), 0, st, src, dst, d, ld, ni,
+  hipLaunchKernelGGL(sketch_permute_kernel, dim3(ni), dim3(128), 0, st, current_gate(), src, dst, d, ld, ni,
                      (const long*)jsk);
   QRCP_LAUNCHED("sketch_permute");
   return QRCP_OK;
 }
 
 // column copies driven by the plan; grid.y = column slot, grid.x = row blocks
-__global__ void place_gather_kernel(const double* A, long lda, long m, int kmax, const long* plan,
+__global__ void place_gather_kernel(Gate gt, const double* A, long lda, long m, int kmax, const long* plan,
                                     double* tmp, long ldt) {
+  QRCP_GATE(gt);
   const int t = blockIdx.y;
   const long r = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (r >= m) return;
   tmp[r + t * ldt] = A[r + plan[8 + t] * lda];
 }
 
-__global__ void place_displace_kernel(double* A, long lda, long m, int kmax, const long* plan) {
+__global__ void place_displace_kernel(Gate gt, double* A, long lda, long m, int kmax, const long* plan) {
+  QRCP_GATE(gt);
   const int q = blockIdx.y;
   if (q >= plan[0]) return;
   const long r = blockIdx.x * (long)blockDim.x + threadIdx.x;
@@ -148,8 +154,9 @@ __global__ void place_displace_kernel(double* A, long lda, long m, int kmax, con
   A[r + fslot * lda] = A[r + dslot * lda];
 }
 
-__global__ void place_scatter_kernel(double* A, long lda, long m, long s, const double* tmp,
+__global__ void place_scatter_kernel(Gate gt, double* A, long lda, long m, long s, const double* tmp,
                                      long ldt) {
+  QRCP_GATE(gt);
   const int t = blockIdx.y;
   const long r = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (r >= m) return;
@@ -160,24 +167,26 @@ int launch_place_columns(double* A, i64 lda, i64 m, i64 s, int kmax, const i64* 
                          i64 ldt, hipStream_t st) {
   if (kmax <= 0 || m <= 0) return QRCP_OK;
   dim3 grid((m + 255) / 256, kmax);
-  hipLaunchKernelGGL(place_gather_kernel, grid, dim3(256), 0, st, A, lda, m, kmax,
+  hipLaunchKernelGGL(place_gather_kernel, grid, dim3(256), 0, st, current_gate(), A, lda, m, kmax,
                      (const long*)plan, tmp, ldt);
-  hipLaunchKernelGGL(place_displace_kernel, grid, dim3(256), 0, st, A, lda, m, kmax,
+  hipLaunchKernelGGL(place_displace_kernel, grid, dim3(256), 0, st, current_gate(), A, lda, m, kmax,
                      (const long*)plan);
-  hipLaunchKernelGGL(place_scatter_kernel, grid, dim3(256), 0, st, A, lda, m, s, tmp, ldt);
+  hipLaunchKernelGGL(place_scatter_kernel, grid, dim3(256), 0, st, current_gate(), A, lda, m, s, tmp, ldt);
   QRCP_LAUNCHED("place_columns");
   return QRCP_OK;
 }
 
-__global__ void final_gather_kernel(const double* A, long lda, long m, long l, const long* phys,
+__global__ void final_gather_kernel(Gate gt, const double* A, long lda, long m, long l, const long* phys,
                                     double* tmp) {
+  QRCP_GATE(gt);
   const long t = blockIdx.y;
   const long r = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (r >= m) return;
   tmp[r + t * m] = A[r + phys[l + t] * lda];
 }
 
-__global__ void final_scatter_kernel(double* A, long lda, long m, long l, const double* tmp) {
+__global__ void final_scatter_kernel(Gate gt, double* A, long lda, long m, long l, const double* tmp) {
+  QRCP_GATE(gt);
   const long t = blockIdx.y;
   const long r = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (r >= m) return;
@@ -191,40 +200,42 @@ int launch_final_permute(double* A, i64 lda, i64 m, i64 l, i64 n, const i64* phy
   for (i64 c0 = 0; c0 < cnt; c0 += 65535) {
     const i64 cc = std::min<i64>(65535, cnt - c0);
     dim3 grid((m + 255) / 256, cc);
-    hipLaunchKernelGGL(final_gather_kernel, grid, dim3(256), 0, st, A, lda, m, l + c0,
+    hipLaunchKernelGGL(final_gather_kernel, grid, dim3(256), 0, st, current_gate(), A, lda, m, l + c0,
                        (const long*)phys, tmp + c0 * m);
   }
   for (i64 c0 = 0; c0 < cnt; c0 += 65535) {
     const i64 cc = std::min<i64>(65535, cnt - c0);
     dim3 grid((m + 255) / 256, cc);
-    hipLaunchKernelGGL(final_scatter_kernel, grid, dim3(256), 0, st, A, lda, m, l + c0,
+    hipLaunchKernelGGL(final_scatter_kernel, grid, dim3(256), 0, st, current_gate(), A, lda, m, l + c0,
                        tmp + c0 * m);
   }
   QRCP_LAUNCHED("final_permute");
   return QRCP_OK;
 }
 
-__global__ void jpiv_out_kernel(const long* J, long n, long base, long* out) {
+__global__ void jpiv_out_kernel(Gate gt, const long* J, long n, long base, long* out) {
+  QRCP_GATE(gt);
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (i < n) out[i] = J[i] + base;
 }
 
 int launch_jpiv_out(const i64* J, i64 n, i64 base, i64* out, hipStream_t st) {
   if (n <= 0) return QRCP_OK;
-  hipLaunchKernelGGL(jpiv_out_kernel, dim3((n + 255) / 256), dim3(256), 0, st, (const long*)J, n,
+  hipLaunchKernelGGL(jpiv_out_kernel, dim3((n + 255) / 256), dim3(256), 0, st, current_gate(), (const long*)J, n,
                      base, (long*)out);
   QRCP_LAUNCHED("jpiv_out");
   return QRCP_OK;
 }
 
-__global__ void iota_kernel(long* x, long n) {
+__global__ void iota_kernel(Gate gt, long* x, long n) {
+  QRCP_GATE(gt);
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (i < n) x[i] = i;
 }
 
 int launch_iota(i64* x, i64 n, hipStream_t st) {
   if (n <= 0) return QRCP_OK;
-  hipLaunchKernelGGL(iota_kernel, dim3((n + 255) / 256), dim3(256), 0, st, (long*)x, n);
+  hipLaunchKernelGGL(iota_kernel, dim3((n + 255) / 256), dim3(256), 0, st, current_gate(), (long*)x, n);
   QRCP_LAUNCHED("iota");
   return QRCP_OK;
 }

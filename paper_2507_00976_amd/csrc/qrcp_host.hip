@@ -27,6 +27,11 @@ int launch_hh_leaf(double* A, i64 lda, i64 mi, int ib, double* tau, uint64_t* re
 
 static thread_local std::string g_last_error;
 
+Gate& current_gate() {
+  static thread_local Gate g{nullptr, 0, kGateRun};
+  return g;
+}
+
 int launch_resident(const void* fn, dim3 grid, dim3 block, void** params, size_t smem,
                     hipStream_t st) {
   static std::mutex mu;
@@ -149,6 +154,9 @@ struct FactorWs {
   size_t hrec_bytes;
   void* gq;
   size_t gq_bytes;
+  double* psave;   // the panel as placed, for a block that stops before its width
+  LoopCtl* ctl;    // control record of the device-driven loop
+  CallResult* result;  // rank and status of the call
 };
 
 size_t carve_factor(char* base, i64 m, i64 n, i64 b, int d, FactorWs* w, bool hqr = false) {
@@ -186,6 +194,9 @@ size_t carve_factor(char* base, i64 m, i64 n, i64 b, int d, FactorWs* w, bool hq
   // column-pivoted sketch QR scratch (qrcp_wide = 1): reflector scalars and arg-max partials
   w->gq_bytes = sketch_geqp3_ws_bytes(d);
   w->gq = c.take<char>(w->gq_bytes);
+  w->psave = c.take<double>((size_t)m * bb);
+  w->ctl = c.take<LoopCtl>(1);
+  w->result = c.take<CallResult>(1);
   // exchange records of the Householder panel's leaf kernel (qr_tall = 1)
   w->hrec_bytes = hqr ? hh_leaf_records_bytes(m) : 0;
   w->hrec = hqr ? c.take<uint64_t>(w->hrec_bytes / 8 + 1) : nullptr;
@@ -384,15 +395,14 @@ namespace {
 // order, with the same arithmetic (the results are bitwise the same).
 int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size,
                 double sketch_factor, uint64_t seed, double tol, int64_t* jpiv, double* tau,
-                int64_t* rank, const qrcp_opts* opts_in, void* workspace, size_t workspace_bytes,
-                void* stream, bool lookahead) {
+                const qrcp_opts* opts_in, void* workspace, size_t workspace_bytes, void* stream,
+                bool lookahead, int64_t* rank_host, int64_t* rank_dev, int32_t* status_dev) {
   if (m < 0) return -2;
   if (n < 0) return -3;
   if (lda < std::max<int64_t>(1, m)) return -4;
   if (block_size < 1) return -5;
   if (!(sketch_factor >= 1.0)) return -6;
   if (!(tol >= 0.0)) return -8;
-  if (!rank) return -11;
   const qrcp_opts o = read_opts(opts_in);
   if (o.cholqr_passes != 1 && o.cholqr_passes != 2) return -12;
   if (o.sketch_precision < 0 || o.sketch_precision > 1) return -12;
@@ -402,8 +412,11 @@ int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
   if (o.qr_tall != 0 && o.qr_tall != 1) return -12;
   if (o.qrcp_wide != 0 && o.qrcp_wide != 1) return -12;
   if (o.max_rank < 0) return -12;
-  *rank = 0;
-  if (n == 0) return QRCP_OK;
+  if (rank_host) *rank_host = 0;
+  if (n == 0) {
+    if (rank_dev || status_dev) QRCP_TRY(launch_set_result(rank_dev, status_dev, (hipStream_t)stream));
+    return QRCP_OK;
+  }
   if (!A && m > 0) return -1;
   if (!jpiv) return -9;
   if (!tau && m > 0) return -10;
@@ -418,19 +431,20 @@ int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
   if (!workspace || workspace_bytes < need) return QRCP_ERR_WORKSPACE;
   carve_factor((char*)workspace, m, n, b, d, &w, o.qr_tall == 1);
   // columns the loop factors at most: min(m, n), or fewer in truncated mode
-  const i64 lim = o.max_rank > 0 ? std::min(std::min(m, n), (i64)o.max_rank) : std::min(m, n);
+  const i64 mn = std::min(m, n);
+  const i64 lim = o.max_rank > 0 ? std::min(mn, (i64)o.max_rank) : mn;
   hipStream_t st = (hipStream_t)stream;
   const Prec tprec = o.trailing_precision ? Prec::F32 : Prec::F64;
-  if (lim == 0) {
-    // no rows (m = 0): nothing to factor, J is the identity
-    QRCP_TRY(launch_iota(w.J[0], n, st));
-    QRCP_TRY(launch_jpiv_out(w.J[0], n, o.pivot_base, jpiv, st));
-    QRCP_HIP(hipStreamSynchronize(st));
-    return QRCP_OK;
-  }
+  // every launch below passes a gate on the loop's control record
+  GateScope open_gate(Gate{nullptr, 0, kGateRun});
+  QRCP_TRY(launch_loop_init(w.ctl, st));
+  QRCP_TRY(zero_int(w.status, st));
+  QRCP_TRY(launch_iota(w.J[0], n, st));
+  QRCP_TRY(launch_iota(w.phys[0], n, st));
+  QRCP_TRY(launch_iota(w.inv, n, st));
 
   // ---- sketch M^sk = S A (S generated once, stored transposed) ----
-  {
+  if (lim > 0) {
     ProfScope ps(kStSketch, 2.0 * d * m * n, st);
     QRCP_TRY(launch_sketch_operator(w.big, m, d, m, seed, st));
     GemmArgs g = ga(d, (int)n, (int)m, w.big, m, A, lda, w.sk0, d);
@@ -438,19 +452,17 @@ int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
     QRCP_TRY(gemm(true, false, o.sketch_precision ? Prec::BF16 : Prec::F64, g, w.split, kSplitBytes, st));
     QRCP_TRY(launch_sketch_ref(w.sk0, d, d, n, w.colss, w.ref, st));
   }
-  QRCP_TRY(launch_iota(w.J[0], n, st));
-  QRCP_TRY(launch_iota(w.phys[0], n, st));
-  QRCP_TRY(launch_iota(w.inv, n, st));
-  QRCP_TRY(zero_int(w.status, st));
 
   AuxStream* aux = nullptr;
   if (getenv("QRCP_NO_LOOKAHEAD")) lookahead = false;
   if (lookahead) QRCP_TRY(aux_stream(&aux));
   JoinGuard jg{st, aux};
   // the previous block's rank-k update of rows s+k .. m, started on the
-  // second stream once the next block's pivots are known
+  // second stream once the next block's pivots are known (its kernels carry
+  // the gate of the block they belong to)
   struct Pending {
     bool on = false;
+    int blk = 0;
     i64 r0 = 0, r1 = 0, nc = 0;
     int k = 0;
     double* C = nullptr;
@@ -458,6 +470,7 @@ int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
   auto start_pending = [&]() -> int {
     if (!pend.on) return QRCP_OK;
     pend.on = false;
+    GateScope gs(Gate{w.ctl, pend.blk, kGateRun});
     if (!lookahead)
       return apply_qt_rows(w.Y, pend.r0, pend.r1, pend.k, m, pend.C, pend.nc, lda, tprec, w.W2, st);
     QRCP_HIP(hipEventRecord(aux->fork, st));
@@ -467,17 +480,30 @@ int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
     jg.pending = true;
     return QRCP_OK;
   };
+  const int* keff = &w.ctl->k;  // the block's effective width, on the device
   int cur = 0;
-  i64 ell = 0;
-  int status = QRCP_OK;
   // pivot_steps = 1 runs only the block's k_max elimination steps of the
   // GETRF of the sketch (the selected columns are the same; the order of the
   // columns no block selects is not that of Alg. 2)
   const bool lu_all_steps = o.pivot_steps == 0;
-  for (i64 s = 0; s < lim; ) {
+  // Every block is enqueued without reading anything back: each block's
+  // launches are sized for its full width k_max; a one-thread kernel after the
+  // panel's Cholesky factorization (tri_rank for the Householder panel)
+  // records the effective width k and whether the loop stops here.  Later
+  // blocks' kernels then return at once (gate kGateRun); in the block that
+  // stops, columns k .. k_max of the panel become identity reflectors (their
+  // factors padded with the identity, tau = 0), and those panel columns,
+  // saved before the panel QR, get the k reflectors applied like the rest of
+  // the trailing matrix (gate kGateExit); the sketch update runs only in
+  // blocks the loop continues past (gate kGateGoOn).
+  int blk = 0;
+  for (i64 s = 0; s < lim; ++blk) {
     const i64 ni = n - s, mi = m - s;
     const int kmax = (int)std::min<i64>(std::min<i64>(b, lim - s), std::min(ni, mi));
     const i64 c = s + kmax;
+    const bool last = c >= lim;
+    const Gate run{w.ctl, blk, kGateRun}, ex{w.ctl, blk, kGateExit}, goon{w.ctl, blk, kGateGoOn};
+    GateScope gs(run);
     // elimination steps of the sketch's GETRF: all min(d, n_i), bounded by
     // m_i (the sketch of an m_i-row matrix has rank <= m_i: beyond it the
     // Schur complement is zero in exact arithmetic, only a wide matrix's last
@@ -486,11 +512,7 @@ int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
     if (!lu_all_steps) lu_steps = kmax;
     else if (mi < std::min<i64>(d, ni)) lu_steps = (int)mi;
     double* Ablk = A + s + s * lda;  // panel top-left (rows s.., physical column s)
-    // 1. pivots of the sketch (Alg. 2 GETRF on the transpose), all min(d, n_i)
-    // elimination steps by default.  With pivot_steps = 1 only the first kmax
-    // run: partial pivoting at step j depends on the steps before j alone, so
-    // they fix the kmax selected columns, and the later steps only reorder the
-    // columns this block leaves, which the next block selects among again.
+    // 1. pivots of the sketch (Alg. 2 GETRF on the transpose, or GEQP3)
     if (o.qrcp_wide == 1) {
       // column-pivoted QR of the sketch (GEQP3): pivots and R^sk in one pass,
       // pivoting over the same rank bound as the LU (min(d, n_i, m_i) steps)
@@ -541,33 +563,35 @@ int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
       ProfScope ps(kStPerm, 0.0, st);
       QRCP_TRY(launch_place_columns(A, lda, m, s, kmax, w.plan, w.tmp, m, st));
     }
-    int k = 0;
     if (o.qr_tall == 1) {
-      // Householder QR of the panel (GEQRF; Sec. 2.3): the block rank from
-      // tri_rank sets the panel width, then 32-column leaves, each applied to
-      // the rest of the panel
-      int hs[2];
-      QRCP_HIP(hipMemcpyAsync(hs, w.status, sizeof(int), hipMemcpyDeviceToHost, st));
-      QRCP_TRY(read_back(hs + 1, w.kdev, sizeof(int), st));
-      if (hs[0] != QRCP_OK) { status = hs[0]; ell = s; break; }
-      k = hs[1];
-      if (k == 0) { ell = s; break; }
-      ProfScope ps(kStGeqrfPanel, 2.0 * mi * k * k - 2.0 * k * k * k / 3.0, st);
-      for (int s2 = 0; s2 < k; s2 += 32) {
-        const int ib = std::min(32, k - s2);
+      // Householder QR of the panel (GEQRF; Sec. 2.3), 32-column leaves each
+      // applied to the rest of the panel; tri_rank's k is the block's width
+      QRCP_TRY(launch_loop_decide(w.ctl, w.status, w.kdev, blk, kmax, s, c, lim, false, st));
+      {
+        GateScope gx(ex);
+        QRCP_TRY(launch_copy2d(Ablk, lda, w.psave, m, mi, kmax, st));
+      }
+      ProfScope ps(kStGeqrfPanel, 2.0 * mi * kmax * kmax - 2.0 * kmax * kmax * kmax / 3.0, st);
+      for (int s2 = 0; s2 < kmax; s2 += 32) {
+        const int ib = std::min(32, kmax - s2);
         double* Al = Ablk + s2 + (i64)s2 * lda;
         QRCP_TRY(launch_hh_leaf(Al, lda, mi - s2, ib, tau + s + s2, w.hrec, w.hrec_bytes, w.status, st));
-        if (s2 + ib < k) {
+        if (s2 + ib < kmax) {
           QRCP_TRY(launch_copy2d(Al, lda, w.tmp, m, mi - s2, ib, st));
           QRCP_TRY(launch_unit_lower(Al, lda, ib, w.tmp, m, st));
-          QRCP_TRY(apply_qt_clean(w.tmp, mi - s2, ib, m, tau + s + s2, Al + (i64)ib * lda, k - s2 - ib,
-                                  lda, Prec::F64, w.G, w.Rc, b, w.W, w.W2, w.split, kSplitBytes, st));
+          QRCP_TRY(apply_qt_clean(w.tmp, mi - s2, ib, m, tau + s + s2, Al + (i64)ib * lda,
+                                  kmax - s2 - ib, lda, Prec::F64, w.G, w.Rc, b, w.W, w.W2, w.split,
+                                  kSplitBytes, st));
         }
+      }
+      {
+        GateScope gx(ex);
+        QRCP_TRY(launch_zero_tail(tau + s, kmax, keff, st));
       }
       // clean Y (unit lower trapezoidal) for the trailing update; R11 stays
       // in place on and above the panel's diagonal
-      QRCP_TRY(launch_copy2d(Ablk, lda, w.Y, m, mi, k, st));
-      QRCP_TRY(launch_unit_lower(Ablk, lda, k, w.Y, m, st));
+      QRCP_TRY(launch_copy2d(Ablk, lda, w.Y, m, mi, kmax, st));
+      QRCP_TRY(launch_unit_lower(Ablk, lda, kmax, w.Y, m, st));
     } else {
       {
         ProfScope ps(kStCholGram, 4.0 * mi * kmax * kmax, st);
@@ -580,80 +604,109 @@ int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
         QRCP_TRY(gemm(true, false, Prec::F64, ga(kmax, kmax, (int)mi, w.Y, m, w.Y, m, w.G, b), w.split,
                       kSplitBytes, st));
         QRCP_TRY(launch_potrf_mw(w.G, b, kmax, w.info, w.split, kSplitBytes, st));
+        QRCP_TRY(launch_loop_decide(w.ctl, w.status, w.info, blk, kmax, s, c, lim, false, st));
+        GateScope gx(ex);
+        QRCP_TRY(launch_copy2d(Ablk, lda, w.psave, m, mi, kmax, st));
+        QRCP_TRY(launch_pad_identity(w.G, b, kmax, keff, st));
       }
-      int hs[3];
-      QRCP_HIP(hipMemcpyAsync(hs, w.status, sizeof(int), hipMemcpyDeviceToHost, st));
-      QRCP_TRY(read_back(hs + 1, w.info, sizeof(int), st));
-      if (hs[0] != QRCP_OK) { status = hs[0]; ell = s; break; }
-      if (hs[1] < 0) { status = QRCP_ERR_TIMEOUT; ell = s; break; }
-      k = hs[1];
-      if (k == 0) { ell = s; break; }
       // Q = M^pre Rc^{-1}
       {
-      ProfScope psq(kStCholQ, 2.0 * mi * k * k, st);
-      QRCP_TRY(launch_trinv_upper(w.G, b, k, w.Rinv, b, st));
-      if (o.cholqr_passes == 2) {
-        QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, k, k, w.Y, m, w.Rinv, b, w.tmp, m), nullptr, 0, st));
-        QRCP_TRY(gemm(true, false, Prec::F64, ga(k, k, (int)mi, w.tmp, m, w.tmp, m, w.R2, b), w.split, kSplitBytes, st));
-        QRCP_TRY(launch_potrf_mw(w.R2, b, k, w.info, w.split, kSplitBytes, st));
-        QRCP_TRY(read_back(hs + 2, w.info, sizeof(int), st));
-        if (hs[2] < 0) { status = QRCP_ERR_TIMEOUT; ell = s; break; }
-        if (hs[2] < k) {
-          // second pass broke down: keep the columns factored by both passes
-          k = hs[2];
-          if (k == 0) { ell = s; break; }
-          QRCP_TRY(launch_trinv_upper(w.G, b, k, w.Rinv, b, st));
-          QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, k, k, w.Y, m, w.Rinv, b, w.tmp, m), nullptr, 0, st));
+        ProfScope psq(kStCholQ, 2.0 * mi * kmax * kmax, st);
+        QRCP_TRY(launch_trinv_upper(w.G, b, kmax, w.Rinv, b, st));
+        {
+          GateScope gx(ex);
+          QRCP_TRY(launch_mask_k(w.Rinv, b, kmax, keff, st));
         }
-        QRCP_TRY(launch_trinv_upper(w.R2, b, k, w.Uinv, b, st));
-        QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, k, k, w.tmp, m, w.Uinv, b, Ablk, lda), nullptr, 0, st));
-        // Rc <- R2 Rc
-        QRCP_TRY(gemm(false, false, Prec::F64, ga(k, k, k, w.R2, b, w.G, b, w.RcN, b), nullptr, 0, st));
-        QRCP_TRY(launch_copy2d(w.RcN, b, w.G, b, k, k, st));
-      } else {
-        QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, k, k, w.Y, m, w.Rinv, b, Ablk, lda), nullptr, 0, st));
-      }
+        if (o.cholqr_passes == 2) {
+          QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, kmax, kmax, w.Y, m, w.Rinv, b, w.tmp, m),
+                        nullptr, 0, st));
+          QRCP_TRY(gemm(true, false, Prec::F64, ga(kmax, kmax, (int)mi, w.tmp, m, w.tmp, m, w.R2, b),
+                        w.split, kSplitBytes, st));
+          QRCP_TRY(launch_potrf_mw(w.R2, b, kmax, w.info, w.split, kSplitBytes, st));
+          QRCP_TRY(launch_loop_decide(w.ctl, w.status, w.info, blk, kmax, s, c, lim, true, st));
+          {
+            // a second-pass breakdown shrinks the width: redo the first pass's
+            // inverse and Q with it (the block then stops the loop)
+            GateScope gx(ex);
+            QRCP_TRY(launch_pad_identity(w.G, b, kmax, keff, st));
+            QRCP_TRY(launch_trinv_upper(w.G, b, kmax, w.Rinv, b, st));
+            QRCP_TRY(launch_mask_k(w.Rinv, b, kmax, keff, st));
+            QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, kmax, kmax, w.Y, m, w.Rinv, b, w.tmp, m),
+                          nullptr, 0, st));
+            QRCP_TRY(launch_pad_identity(w.R2, b, kmax, keff, st));
+          }
+          QRCP_TRY(launch_trinv_upper(w.R2, b, kmax, w.Uinv, b, st));
+          {
+            GateScope gx(ex);
+            QRCP_TRY(launch_mask_k(w.Uinv, b, kmax, keff, st));
+          }
+          QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, kmax, kmax, w.tmp, m, w.Uinv, b, Ablk, lda),
+                        nullptr, 0, st));
+          // Rc <- R2 Rc
+          QRCP_TRY(gemm(false, false, Prec::F64, ga(kmax, kmax, kmax, w.R2, b, w.G, b, w.RcN, b), nullptr,
+                        0, st));
+          QRCP_TRY(launch_copy2d(w.RcN, b, w.G, b, kmax, kmax, st));
+        } else {
+          QRCP_TRY(gemm(false, false, Prec::F64, ga((int)mi, kmax, kmax, w.Y, m, w.Rinv, b, Ablk, lda),
+                        nullptr, 0, st));
+        }
       }
       // 9. Householder reconstruction: sign-modified LU of the head, Y2 = Q2 U^{-1}
       {
-      ProfScope psr(kStRecon, 2.0 * (mi - k) * k * k + 2.0 * k * k * k, st);
-      QRCP_TRY(launch_headlu_mw(Ablk, lda, k, w.dsig, w.split, kSplitBytes, w.status, st));
-      QRCP_TRY(launch_tau_from_u(Ablk, lda, k, w.dsig, tau + s, st));
-      QRCP_TRY(launch_trinv_upper(Ablk, lda, k, w.Uinv, b, st));
-      if (mi > k) {
-        QRCP_TRY(gemm(false, false, Prec::F64, ga((int)(mi - k), k, k, Ablk + k, lda, w.Uinv, b, w.Y + k, m),
-                      nullptr, 0, st));
-        QRCP_TRY(launch_copy2d(w.Y + k, m, Ablk + k, lda, mi - k, k, st));
-      }
-      QRCP_TRY(launch_unit_lower(Ablk, lda, k, w.Y, m, st));
-      //    R11 = diag(D) Rc Rsk(0:k, 0:k)
-      QRCP_TRY(gemm(false, false, Prec::F64, ga(k, k, k, w.G, b, Rsk, d, w.P, b), nullptr, 0, st));
-      QRCP_TRY(launch_write_r11(w.P, b, k, w.dsig, Ablk, lda, st));
+        ProfScope psr(kStRecon, 2.0 * (mi - kmax) * kmax * kmax + 2.0 * kmax * kmax * kmax, st);
+        QRCP_TRY(launch_headlu_mw(Ablk, lda, kmax, w.dsig, w.split, kSplitBytes, w.status, st));
+        QRCP_TRY(launch_tau_from_u(Ablk, lda, kmax, w.dsig, tau + s, st));
+        {
+          GateScope gx(ex);
+          QRCP_TRY(launch_zero_tail(tau + s, kmax, keff, st));
+        }
+        QRCP_TRY(launch_trinv_upper(Ablk, lda, kmax, w.Uinv, b, st));
+        if (mi > kmax) {
+          QRCP_TRY(gemm(false, false, Prec::F64,
+                        ga((int)(mi - kmax), kmax, kmax, Ablk + kmax, lda, w.Uinv, b, w.Y + kmax, m),
+                        nullptr, 0, st));
+          QRCP_TRY(launch_copy2d(w.Y + kmax, m, Ablk + kmax, lda, mi - kmax, kmax, st));
+        }
+        QRCP_TRY(launch_unit_lower(Ablk, lda, kmax, w.Y, m, st));
+        //    R11 = diag(D) Rc Rsk(0:k, 0:k)
+        QRCP_TRY(gemm(false, false, Prec::F64, ga(kmax, kmax, kmax, w.G, b, Rsk, d, w.P, b), nullptr, 0, st));
+        QRCP_TRY(launch_write_r11(w.P, b, kmax, w.dsig, Ablk, lda, st));
       }
     }
-    // 10-11. trailing update of the physical columns s+k .. n-1 (rows s..m-1)
-    const i64 nc = n - s - k;
-    double* Ct = A + s + (s + k) * lda;
-    QRCP_TRY(apply_qt_w(w.Y, mi, k, m, tau + s, Ct, nc, lda, tprec, w.Tm, w.R11inv, b, w.W, w.W2,
+    // 10-11. trailing update of the physical columns c .. n-1 (rows s..m-1)
+    const i64 nc = n - c;
+    double* Ct = A + s + c * lda;
+    QRCP_TRY(apply_qt_w(w.Y, mi, kmax, m, tau + s, Ct, nc, lda, tprec, w.Tm, w.R11inv, b, w.W, w.W2,
                         w.split, kSplitBytes, st));
-    if (k < kmax || c >= lim) {
-      QRCP_TRY(apply_qt_rows(w.Y, 0, mi, k, m, Ct, nc, lda, tprec, w.W2, st));
-      ell = s + k;
+    {
+      // a block that stops before its width: the k reflectors applied to the
+      // saved panel columns k .. k_max, which become R(0:k, k:k_max) and the
+      // residual rows
+      GateScope gx(ex);
+      QRCP_TRY(apply_qt_wt(w.Y, mi, kmax, m, w.R11inv, b, w.psave, kmax, m, tprec, w.X, w.R2, w.split,
+                           kSplitBytes, st));
+      QRCP_TRY(apply_qt_rows(w.Y, 0, mi, kmax, m, w.psave, kmax, m, tprec, w.R2, st));
+      QRCP_TRY(launch_copy_cols_from(w.psave, m, Ablk, lda, mi, kmax, keff, st));
+    }
+    if (last) {
+      QRCP_TRY(apply_qt_rows(w.Y, 0, mi, kmax, m, Ct, nc, lda, tprec, w.W2, st));
       break;
     }
     // rows s .. s+k (R12) now: the sketch update needs them
-    QRCP_TRY(apply_qt_rows(w.Y, 0, k, k, m, Ct, nc, lda, tprec, w.W2, st));
+    QRCP_TRY(apply_qt_rows(w.Y, 0, kmax, kmax, m, Ct, nc, lda, tprec, w.W2, st));
     // 12. sketch update: M^sk(0:b, c:) = Rsk12 - Rsk11 R11^{-1} R12 (R12 read through the map)
-    ProfScope psu(kStSketchUpdate, 2.0 * b * b * (n - c), st);
-    if (o.cholqr_passes == 1 && o.qr_tall == 0) {
-      // R11 = diag(D) Rc Rsk11, so Rsk11 R11^{-1} = Rc^{-1} diag(D): the
-      // inverse of the Cholesky factor is at hand (Q = M^pre Rc^{-1})
-      QRCP_TRY(launch_scale_upper_cols(w.Rinv, b, w.dsig, (int)b, w.X, b, st));
-    } else {
-      QRCP_TRY(launch_trinv_upper(Ablk, lda, (int)b, w.R11inv, b, st));
-      QRCP_TRY(gemm(false, false, Prec::F64, ga((int)b, (int)b, (int)b, Rsk, d, w.R11inv, b, w.X, b), nullptr, 0, st));
-    }
     {
+      GateScope gg(goon);
+      ProfScope psu(kStSketchUpdate, 2.0 * b * b * (n - c), st);
+      if (o.cholqr_passes == 1 && o.qr_tall == 0) {
+        // R11 = diag(D) Rc Rsk11, so Rsk11 R11^{-1} = Rc^{-1} diag(D): the
+        // inverse of the Cholesky factor is at hand (Q = M^pre Rc^{-1})
+        QRCP_TRY(launch_scale_upper_cols(w.Rinv, b, w.dsig, (int)b, w.X, b, st));
+      } else {
+        QRCP_TRY(launch_trinv_upper(Ablk, lda, (int)b, w.R11inv, b, st));
+        QRCP_TRY(gemm(false, false, Prec::F64, ga((int)b, (int)b, (int)b, Rsk, d, w.R11inv, b, w.X, b),
+                      nullptr, 0, st));
+      }
       GemmArgs g = ga((int)b, (int)(n - c), (int)b, w.X, b, A + s, lda, w.sk0 + c * d, d, -1.0, 1.0);
       g.bcol = w.phys[cur] + c;
       QRCP_TRY(gemm(false, false, Prec::F64, g, nullptr, 0, st));
@@ -661,30 +714,32 @@ int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
     // rows s+k .. m: deferred to the next block, on the second stream
     // (QRCP_NO_LOOKAHEAD=1 keeps them on the caller's stream, for diagnosis)
     pend.on = true;
-    pend.r0 = k;
+    pend.blk = blk;
+    pend.r0 = kmax;
     pend.r1 = mi;
-    pend.k = k;
+    pend.k = kmax;
     pend.C = Ct;
     pend.nc = nc;
     s = c;
-    ell = s;
   }
   QRCP_TRY(start_pending());
   QRCP_TRY(jg.join());
-  if (status == QRCP_OK && ell < std::min(m, n)) {
-    QRCP_TRY(launch_fill(tau + ell, 1, std::min(m, n) - ell, 1, 0.0, st));
+  // the live maps, tau(l:) = 0, the unplaced columns in logical order, rank and status
+  i64* rdev = rank_dev ? rank_dev : (i64*)&w.result->rank;
+  int* sdev = status_dev ? status_dev : &w.result->status;
+  QRCP_TRY(launch_loop_final(w.ctl, A, lda, m, n, w.J[0], w.J[1], w.phys[0], w.phys[1], tau, mn,
+                             w.big, w.status, rdev, sdev, st));
+  QRCP_TRY(launch_jpiv_out(w.J[0], n, o.pivot_base, jpiv, st));
+  if (!rank_host) return QRCP_OK;
+  // the blocking form: one read-back of rank and status for the whole call
+  CallResult res{};
+  if (rank_dev || status_dev) {
+    QRCP_TRY(launch_copy_result(rdev, sdev, w.result, st));
   }
-  if (status == QRCP_OK && ell < n) {
-    QRCP_TRY(launch_final_permute(A, lda, m, ell, n, w.phys[cur], w.big, st));
-  }
-  QRCP_TRY(launch_jpiv_out(w.J[cur], n, o.pivot_base, jpiv, st));
-  int fin = QRCP_OK;
-  QRCP_TRY(read_back(&fin, w.status, sizeof(int), st));  // a wait that ran out after the last check
-  if (status == QRCP_OK && fin != QRCP_OK) status = fin;
-  *rank = ell;
-  return status;
+  QRCP_TRY(read_back(&res, w.result, sizeof(CallResult), st));
+  *rank_host = res.rank;
+  return res.status;
 }
-
 }  // namespace
 }  // namespace qrcp
 
@@ -694,8 +749,19 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
                 double sketch_factor, uint64_t seed, double tol, int64_t* jpiv, double* tau,
                 int64_t* rank, const qrcp_opts* opts, void* workspace, size_t workspace_bytes,
                 void* stream) {
-  return factor_impl(A, m, n, lda, block_size, sketch_factor, seed, tol, jpiv, tau, rank, opts,
-                     workspace, workspace_bytes, stream, true);
+  if (!rank) return -11;
+  return factor_impl(A, m, n, lda, block_size, sketch_factor, seed, tol, jpiv, tau, opts, workspace,
+                     workspace_bytes, stream, true, rank, nullptr, nullptr);
+}
+
+int qrcp_factor_async(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size,
+                      double sketch_factor, uint64_t seed, double tol, int64_t* jpiv, double* tau,
+                      int64_t* rank_dev, int32_t* status_dev, const qrcp_opts* opts,
+                      void* workspace, size_t workspace_bytes, void* stream) {
+  if (!rank_dev) return -11;
+  if (!status_dev) return -12;
+  return factor_impl(A, m, n, lda, block_size, sketch_factor, seed, tol, jpiv, tau, opts, workspace,
+                     workspace_bytes, stream, true, nullptr, rank_dev, status_dev);
 }
 
 }  // extern "C"
@@ -747,8 +813,9 @@ int qrcp_factor_noalloc(double* A, int64_t m, int64_t n, int64_t lda, int64_t bl
                         double* tau, int64_t* rank, const qrcp_opts* opts, void* stream) {
   // qrcp_factor's own checks, all on the host before any launch: without a
   // workspace the call ends at the workspace check if everything else holds
-  const int pre = factor_impl(A, m, n, lda, block_size, sketch_factor, seed, tol, jpiv, tau, rank,
-                              opts, nullptr, 0, stream, false);
+  if (!rank) return -11;
+  const int pre = factor_impl(A, m, n, lda, block_size, sketch_factor, seed, tol, jpiv, tau, opts,
+                              nullptr, 0, stream, false, rank, nullptr, nullptr);
   if (pre != QRCP_ERR_WORKSPACE) return pre;
   const size_t need = qrcp_workspace_size(m, n, block_size, sketch_factor, opts);
   if (need > kNoAllocBytes) {
@@ -760,8 +827,8 @@ int qrcp_factor_noalloc(double* A, int64_t m, int64_t n, int64_t lda, int64_t bl
   void* ws = nullptr;
   QRCP_TRY(scratch_address(&ws));
   // no second stream: the library creates nothing on this path
-  return factor_impl(A, m, n, lda, block_size, sketch_factor, seed, tol, jpiv, tau, rank, opts,
-                     ws, kNoAllocBytes, stream, false);
+  return factor_impl(A, m, n, lda, block_size, sketch_factor, seed, tol, jpiv, tau, opts, ws,
+                     kNoAllocBytes, stream, false, rank, nullptr, nullptr);
 }
 
 // ----------------------------------------------------------------------------

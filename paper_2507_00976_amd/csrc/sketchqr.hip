@@ -115,7 +115,8 @@ __device__ void apply_panel_mfma(double* sC, int d, int ldc, const double* V, in
 }
 
 template <int PW>
-__global__ __launch_bounds__(NT) void sketch_head_kernel(HeadArgs a) {
+__global__ __launch_bounds__(NT) void sketch_head_kernel(Gate gt, HeadArgs a) {
+  QRCP_GATE(gt);
   extern __shared__ double smem[];
   const int d = a.d, dh = a.dh;
   const int ldc = d + 1;                   // odd column stride: no LDS bank conflicts across columns
@@ -329,7 +330,8 @@ constexpr int PWR = 32;  // panel width
 constexpr int LDP = 33;  // padded LDS row stride
 
 template <int NR2>
-__global__ __launch_bounds__(NT) void sketch_head_reg_kernel(HeadArgs a) {
+__global__ __launch_bounds__(NT) void sketch_head_reg_kernel(Gate gt, HeadArgs a) {
+  QRCP_GATE(gt);
   static_assert(NR2 % 4 == 0, "row slabs come in groups of four");
   extern __shared__ double smem[];
   constexpr int DP = 16 * NR2;             // rows held (>= d); rows d.. are zero
@@ -812,7 +814,8 @@ int run_sketch_qr(const double* B, int d, i64 ni, i64 ldb, double* R, i64 ldr, v
   const bool tfull = d <= 320;  // the register head builds T of all panels
   HeadArgs args{B, (long)ldb, d, dh, pw, R, (long)ldr, V, tau, Tp, flags, status_dev,
                 tfull ? T : nullptr, flags + np};
-  void* params[] = {&args};
+  Gate gt = current_gate();
+  void* params[] = {&gt, &args};
   if (d <= 320) {
     const int nr2 = d <= 128 ? 8 : (d <= 192 ? 12 : 20);
     const size_t dp = (size_t)16 * nr2;

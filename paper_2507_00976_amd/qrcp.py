@@ -54,6 +54,8 @@ def _sig(name, res, *args):
 _sig("qrcp_workspace_size", _sz, _i64, _i64, _i64, _dbl, ctypes.POINTER(QrcpOpts))
 _sig("qrcp_factor", ctypes.c_int, _vp, _i64, _i64, _i64, _i64, _dbl, _u64, _dbl, _vp, _vp,
      ctypes.POINTER(_i64), ctypes.POINTER(QrcpOpts), _vp, _sz, _vp)
+_sig("qrcp_factor_async", ctypes.c_int, _vp, _i64, _i64, _i64, _i64, _dbl, _u64, _dbl, _vp, _vp,
+     _vp, _vp, ctypes.POINTER(QrcpOpts), _vp, _sz, _vp)
 _sig("qrcp_noalloc_max_bytes", _sz)
 _sig("qrcp_factor_noalloc", ctypes.c_int, _vp, _i64, _i64, _i64, _i64, _dbl, _u64, _dbl, _vp, _vp,
      ctypes.POINTER(_i64), ctypes.POINTER(QrcpOpts), _vp)
@@ -113,7 +115,7 @@ _sig("qrcp_profile_read", ctypes.c_int, _i32, ctypes.POINTER(ctypes.c_double), c
      ctypes.POINTER(ctypes.c_double))
 
 EXPORTED = ["qrcp_profile_enable", "qrcp_profile_num_stages", "qrcp_profile_stage_name",
-            "qrcp_profile_read", "qrcp_workspace_size", "qrcp_factor", "qrcp_noalloc_max_bytes",
+            "qrcp_profile_read", "qrcp_workspace_size", "qrcp_factor", "qrcp_factor_async", "qrcp_noalloc_max_bytes",
             "qrcp_factor_noalloc", "qrcp_geqrf_workspace_size", "qrcp_geqrf",
             "qrcp_status_string", "qrcp_last_error", "qrcp_sketch_operator", "qrcp_philox",
             "qrcp_sketch", "qrcp_lu_workspace_size", "qrcp_lu_pivots",
@@ -198,6 +200,30 @@ def factor(A: torch.Tensor, block_size: int, sketch_factor: float = 1.25, seed: 
                           workspace.numel(), _stream(stream))
     _check(rc, "qrcp_factor")
     return A, jpiv, tau, int(rank.value)
+
+
+def factor_async(A: torch.Tensor, block_size: int, sketch_factor: float = 1.25, seed: int = 42,
+                 tol: float = 0.0, *, workspace: torch.Tensor | None = None, stream=None, **opts):
+    """qrcp_factor_async: enqueues the whole factorization on the stream and
+    returns at once -> (A, jpiv, tau, rank_dev, status_dev); rank_dev (int64)
+    and status_dev (int32) are one-element device tensors, valid once the
+    stream has passed the call.  The returned tensors and the workspace must
+    stay alive until then."""
+    ptr, m, n, lda = _cm(A, "A")
+    o = _opts(**opts)
+    need = int(_lib.qrcp_workspace_size(m, n, block_size, sketch_factor, ctypes.byref(o)))
+    if workspace is None:
+        workspace = _ws(need, A.device)
+    jpiv = torch.empty(n, dtype=torch.int64, device=A.device)
+    tau = torch.empty(min(m, n), dtype=torch.float64, device=A.device)
+    rank_dev = torch.empty(1, dtype=torch.int64, device=A.device)
+    status_dev = torch.empty(1, dtype=torch.int32, device=A.device)
+    rc = _lib.qrcp_factor_async(ptr, m, n, lda, block_size, sketch_factor, seed, tol,
+                                jpiv.data_ptr(), tau.data_ptr(), rank_dev.data_ptr(),
+                                status_dev.data_ptr(), ctypes.byref(o), workspace.data_ptr(),
+                                workspace.numel(), _stream(stream))
+    _check(rc, "qrcp_factor_async")
+    return A, jpiv, tau, rank_dev, status_dev
 
 
 def noalloc_max_bytes() -> int:

@@ -114,3 +114,22 @@ def test_noalloc_checks_before_launch(lib):
     assert b"above the fixed" in L.qrcp_last_error()
     # serving-sized problems fit
     assert lib.workspace_size(4096, 1024, 64, 1.25) <= lib.noalloc_max_bytes()
+
+
+def test_async_checks_before_launch(lib):
+    """qrcp_factor_async: the same host checks as qrcp_factor, before any launch;
+    n above the pivot selection's grid (40000) is refused up front."""
+    L = lib._lib
+    nul = None
+    fake = ctypes.c_void_p(16)
+    # rank_dev / status_dev missing
+    assert L.qrcp_factor_async(fake, 8, 4, 8, 2, 1.25, 1, 0.0, fake, fake, nul, fake, None, fake, 1 << 30,
+                               nul) == -11
+    assert L.qrcp_factor_async(fake, 8, 4, 8, 2, 1.25, 1, 0.0, fake, fake, fake, nul, None, fake, 1 << 30,
+                               nul) == -12
+    assert L.qrcp_factor_async(nul, -1, 4, 4, 2, 1.25, 1, 0.0, nul, nul, fake, fake, None, nul, 0, nul) == -2
+    assert L.qrcp_factor_async(nul, 8, 4, 4, 2, 1.25, 1, 0.0, nul, nul, fake, fake, None, nul, 0, nul) == -4
+    assert L.qrcp_factor_async(fake, 40000, 40000, 40000, 256, 1.25, 1, 0.0, fake, fake, fake, fake, None,
+                               nul, 0, nul) == lib.QRCP_ERR_UNSUPPORTED
+    assert L.qrcp_factor_async(fake, 64, 32, 64, 8, 1.25, 1, 0.0, fake, fake, fake, fake, None, nul, 0,
+                               nul) == lib.QRCP_ERR_WORKSPACE
