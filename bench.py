@@ -109,6 +109,88 @@ def write_traffic(fetch_csv, write_csv, n):
     print(json.dumps(rec))
 
 
+def pmc_table(paths, n):
+    """Markdown table per kernel from rocprofv3 counter-collection CSVs of one
+    `bench.py` command (one CSV per counter pass): launches, average duration
+    in the counter run, and per counter family the derived figures --
+    FETCH_SIZE / WRITE_SIZE as HBM GB per launch (each calibrated with the
+    run's largest device-to-device copy, the restore of the n x n input: 8 n^2
+    bytes read and written) and GB/s; SQ_INSTS_VALU_MFMA_MOPS_* as TFLOP/s
+    (512 flops per MOP) and SQ_VALU_MFMA_BUSY_CYCLES over GRBM_GUI_ACTIVE
+    (summed over the 8 XCDs) as the busy share of the 1024 SIMDs' MFMA units."""
+    import csv
+    import re
+    per = {}     # (dispatch) -> {"name", "dur", counter: value}
+    for path in paths:
+        with open(path, newline="") as f:
+            for row in csv.DictReader(f):
+                low = {k.lower(): v for k, v in row.items() if k}
+                did = int(low.get("dispatch_id") or low.get("correlation_id"))
+                rec = per.setdefault(did, {"name": low.get("kernel_name", ""), "dur": None})
+                try:
+                    rec["dur"] = (int(low["end_timestamp"]) - int(low["start_timestamp"])) * 1e-9
+                except (KeyError, ValueError):
+                    pass
+                c = low.get("counter_name")
+                rec[c] = rec.get(c, 0.0) + float(low["counter_value"])
+    copy_kib = 8.0 * n * n / 1024.0
+    scale = {}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        cp = [r[c] for r in per.values() if c in r and "copyBuffer" in r["name"]]
+        if cp:
+            scale[c] = copy_kib / max(cp)
+
+    def short(name):
+        name = re.sub(r"\(.*$", "", name)
+        name = re.sub(r"^void ", "", name).replace("qrcp::", "")
+        return name
+
+    groups = {}
+    for r in per.values():
+        if "copyBuffer" in r["name"] or not r["name"]:
+            continue
+        g = groups.setdefault(short(r["name"]), [])
+        g.append(r)
+    cols = ["kernel", "launches", "avg ms (counter run)"]
+    have = set(k for r in per.values() for k in r)
+    if "FETCH_SIZE" in have and "FETCH_SIZE" in scale:
+        cols += ["HBM read GB/launch"]
+    if "WRITE_SIZE" in have and "WRITE_SIZE" in scale:
+        cols += ["HBM write GB/launch"]
+    if {"FETCH_SIZE", "WRITE_SIZE"} <= have and len(scale) == 2:
+        cols += ["HBM GB/s"]
+    mf = [c for c in ("SQ_INSTS_VALU_MFMA_MOPS_F64", "SQ_INSTS_VALU_MFMA_MOPS_BF16") if c in have]
+    for c in mf:
+        cols += [("FP64" if c.endswith("F64") else "BF16") + " MFMA TFLOP/s"]
+    if {"SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE"} <= have:
+        cols += ["MFMA busy %"]
+    lines = ["| " + " | ".join(cols) + " |", "|" + "---|" * len(cols)]
+    rows = []
+    for name, rs in groups.items():
+        dur = sum(r["dur"] or 0.0 for r in rs)
+        cells = [f"`{name}`", str(len(rs)), f"{dur / len(rs) * 1e3:.3f}"]
+        rd = wr = None
+        if "HBM read GB/launch" in cols:
+            rd = sum(r.get("FETCH_SIZE", 0.0) for r in rs) * scale["FETCH_SIZE"] * 1024.0
+            cells.append(f"{rd / len(rs) / 1e9:.4f}")
+        if "HBM write GB/launch" in cols:
+            wr = sum(r.get("WRITE_SIZE", 0.0) for r in rs) * scale["WRITE_SIZE"] * 1024.0
+            cells.append(f"{wr / len(rs) / 1e9:.4f}")
+        if "HBM GB/s" in cols:
+            cells.append(f"{(rd + wr) / dur / 1e9:.0f}" if dur > 0 else "")
+        for c in mf:
+            fl = sum(r.get(c, 0.0) for r in rs) * 512.0
+            cells.append(f"{fl / dur / 1e12:.2f}" if dur > 0 else "")
+        if "MFMA busy %" in cols:
+            busy = sum(r.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) for r in rs)
+            act = sum(r.get("GRBM_GUI_ACTIVE", 0.0) for r in rs) / 8.0
+            cells.append(f"{100.0 * busy / (act * 1024.0):.1f}" if act > 0 else "")
+        rows.append((dur, "| " + " | ".join(cells) + " |"))
+    rows.sort(key=lambda t: -t[0])
+    lines += [r for _, r in rows if _ > 0]
+    print("\n".join(lines))
+
+
 def canonical_flops(m, n):
     return 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
 
@@ -264,18 +346,18 @@ def run_lowrank(args, torch, qrcp, WD):
     print(json.dumps(out), flush=True)
 
 
-def run_serving(args, torch, qrcp, WD):
+def serving_run(args, torch, qrcp, WD, nreq, pool, loads):
     """Poisson stream of independent requests: m log-uniform in [256, 4096], n log-uniform in
     [64, min(m, 1024)], b = min(64, n), d = ceil(1.25 b), spectrum geometric / (i+1)^-1 /
-    exact rank n/2 (tol 1e-13), served by the library's request server."""
+    exact rank n/2 (tol 1e-13), served by the library's request server.  Returns the record
+    of the open-loop run at loads[0] x the measured closed-loop capacity (and the others)."""
     import numpy as np
     dev = torch.device("cuda:0")
     rng = np.random.default_rng(args.seed)
-    nreq = args.requests
     # the stream draws from a pool of distinct matrices (request i factors
     # matrix i % pool, restored from a pristine copy; a buffer is refilled only
     # after its previous request has finished)
-    pool = min(nreq, 1000)
+    pool = min(nreq, pool)
     pshapes = []
     for i in range(pool):
         m = int(np.exp(rng.uniform(np.log(256), np.log(4096))))
@@ -335,7 +417,7 @@ def run_serving(args, torch, qrcp, WD):
         log(f"closed loop: {nreq} requests in {wall:.2f}s = {cap:.1f} req/s, "
             f"{sum(flops) / wall / 1e9:.1f} GFLOP/s")
         open_loop = {}
-        for load in (args.load, 0.5):
+        for load in loads:
             lam_l = load * cap
             gaps = rng.exponential(1.0 / lam_l, nreq)
             times = np.cumsum(gaps) - gaps[0]
@@ -344,28 +426,35 @@ def run_serving(args, torch, qrcp, WD):
             open_loop[load] = (lam_l, wall_l, res_l, lat_l)
             log(f"open loop at {lam_l:.1f} req/s offered ({load}x): {nreq / wall_l:.1f} req/s, "
                 f"p50 {np.percentile(lat_l, 50):.3f} ms, p99 {np.percentile(lat_l, 99):.3f} ms")
-        lam, wall, res, lat = open_loop[args.load]
+        lam, wall, res, lat = open_loop[loads[0]]
     ranks_ok = all(r[3] == (shapes[i][1] // 2 if shapes[i][2] == 2 else shapes[i][1])
                    for i, r in enumerate(res))
-    out = {"metric": "QRCP serving req/s + p99 latency", "value": round(nreq / wall, 2),
+    return {"req_s": round(nreq / wall, 2),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "mean_ms": round(float(lat.mean()), 3),
+            "closed_loop_req_s": round(cap, 2), "offered_req_s": round(lam, 2),
+            "aggregate_gflops": round(sum(flops) / wall / 1e9, 1), "ranks_as_expected": ranks_ok,
+            "open_loop": {f"{ld}x": {"offered_req_s": round(v[0], 2),
+                                     "req_s": round(nreq / v[1], 2),
+                                     "p50_ms": round(float(np.percentile(v[3], 50)), 3),
+                                     "p99_ms": round(float(np.percentile(v[3], 99)), 3)}
+                          for ld, v in open_loop.items()},
+            "workload": (f"{nreq} requests over {pool} distinct matrices, m in [256,4096], "
+                         f"n in [64,min(m,1024)] log-uniform, b=min(64,n), d=ceil(1.25b), "
+                         f"Poisson arrivals at {loads[0]}x closed-loop capacity"),
+            "slots": args.slots}
+
+
+def run_serving(args, torch, qrcp, WD):
+    """The serving workload on its own: 10 000 requests over 1000 matrices by default."""
+    rec = serving_run(args, torch, qrcp, WD, args.requests, 1000, (args.load, 0.5))
+    out = {"metric": "QRCP serving req/s + p99 latency", "value": rec["req_s"],
            "unit": "req/s", "n_gpus": 1, "higher_is_better": True,
-           "p50_ms": round(float(np.percentile(lat, 50)), 3),
-           "p99_ms": round(float(np.percentile(lat, 99)), 3),
-           "mean_ms": round(float(lat.mean()), 3),
-           "closed_loop_req_s": round(cap, 2), "offered_req_s": round(lam, 2),
-           "aggregate_gflops": round(sum(flops) / wall / 1e9, 1), "ranks_as_expected": ranks_ok,
-           "open_loop": {f"{ld}x": {"offered_req_s": round(v[0], 2),
-                                    "req_s": round(nreq / v[1], 2),
-                                    "p50_ms": round(float(np.percentile(v[3], 50)), 3),
-                                    "p99_ms": round(float(np.percentile(v[3], 99)), 3)}
-                         for ld, v in open_loop.items()},
            "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"{nreq} requests over {pool} distinct matrices, m in [256,4096], "
-                                  f"n in [64,min(m,1024)] log-uniform, b=min(64,n), d=ceil(1.25b), "
-                                  f"Poisson arrivals at {args.load}x (and 0.5x) closed-loop capacity",
-                      "slots": args.slots}}
-    log(f"open loop at {lam:.1f} req/s offered: {nreq / wall:.1f} req/s, p50 {out['p50_ms']} ms, "
-        f"p99 {out['p99_ms']} ms")
+           "config": {"workload": rec["workload"], "slots": args.slots}}
+    out.update({k: v for k, v in rec.items() if k not in ("workload", "slots")})
+    log(f"open loop: {out['value']} req/s, p50 {out['p50_ms']} ms, p99 {out['p99_ms']} ms")
     print(json.dumps(out), flush=True)
 
 
@@ -380,6 +469,8 @@ def main():
     ap.add_argument("--seed", type=int, default=20250702)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
     ap.add_argument("--no-geqrf", action="store_true")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the compact serving run of the default line")
     ap.add_argument("--breakdown", action="store_true", help="extra run timing every stage")
     ap.add_argument("--context", action="store_true", help="also time torch.geqrf (rocSOLVER)")
     ap.add_argument("--workload", choices=["headline", "precision", "lowrank", "serving"],
@@ -388,7 +479,7 @@ def main():
                          "FP32-trailing variants; lowrank: 32768^2 rank-4096 detection; serving: "
                          "Poisson stream of mixed-shape requests through the request server")
     ap.add_argument("--requests", type=int, default=10000, help="serving: number of requests")
-    ap.add_argument("--slots", type=int, default=4, help="serving: concurrent requests")
+    ap.add_argument("--slots", type=int, default=8, help="serving: concurrent requests")
     ap.add_argument("--load", type=float, default=0.8,
                     help="serving: offered rate as a fraction of the closed-loop capacity")
     ap.add_argument("--m", type=int, default=0, help="rows (precision/lowrank workloads)")
@@ -401,10 +492,20 @@ def main():
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no benchmark: turn two rocprofv3 counter-collection CSVs (FETCH_SIZE, "
                          "WRITE_SIZE) of a Gaussian-input run into the committed traffic record")
+    ap.add_argument("--sketch-bf16", action="store_true",
+                    help="headline workload with the BF16 sketch GEMM and CholQR2 (for counter "
+                         "runs of that GEMM; the JSON line then says so in config.sketch)")
+    ap.add_argument("--pmc-table", nargs="+", metavar="CSV",
+                    help="no benchmark: print a per-kernel table of the counters in rocprofv3 "
+                         "counter-collection CSVs of one bench.py command (HBM bytes, MFMA rate "
+                         "and busy share)")
     args = ap.parse_args()
 
     if args.write_traffic:
         write_traffic(args.write_traffic[0], args.write_traffic[1], args.n)
+        return
+    if args.pmc_table:
+        pmc_table(args.pmc_table, args.n)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the method is "
@@ -439,12 +540,16 @@ def main():
     torch.cuda.synchronize()
     log(f"generated A {m}x{n} in {time.perf_counter() - t0:.1f}s")
     A = qrcp.colmajor(A0.clone())
-    ws = torch.empty(qrcp.workspace_size(m, n, b, args.gamma), dtype=torch.uint8, device=dev)
+    # --sketch-bf16: the BF16 sketch GEMM (with CholQR2), for counter runs of
+    # that GEMM; the headline figure is the FP64 path
+    hopts = {"sketch_precision": 1, "cholqr_passes": 2} if args.sketch_bf16 else {}
+    ws = torch.empty(qrcp.workspace_size(m, n, b, args.gamma, **hopts), dtype=torch.uint8,
+                     device=dev)
     log(f"workspace {ws.numel() / 2**30:.2f} GiB")
 
     def step():
         A.copy_(A0)
-        return qrcp.factor(A, b, args.gamma, 42, 0.0, workspace=ws)
+        return qrcp.factor(A, b, args.gamma, 42, 0.0, workspace=ws, **hopts)
 
     for _ in range(args.warmup):
         step()
@@ -511,6 +616,8 @@ def main():
         "orthogonality": orthogonality,
         "roofline": roofline,
     }
+    if args.sketch_bf16:
+        out["config"]["sketch"] = "bf16 (CholQR2)"
 
     if not args.no_geqrf:
         wsg = torch.empty(qrcp.geqrf_workspace_size(m, n, b), dtype=torch.uint8, device=dev)
@@ -554,6 +661,12 @@ def main():
             if v[1]:
                 log(f"  {k:26s} {v[0]:9.3f} ms  {v[1]:5d} launches  "
                     f"{(v[2] / (v[0] / 1e3) / 1e12 if v[0] > 0 and v[2] else 0):7.2f} TFLOP/s")
+
+    if not args.no_serving:
+        # the metric's second half on the same box: a compact serving run
+        # (2000 requests over 200 matrices, Poisson arrivals at 0.8x the
+        # measured closed-loop capacity)
+        out["serving"] = serving_run(args, torch, qrcp, WD, 2000, 200, (args.load,))
 
     if not args.no_cpu:
         from threadpoolctl import threadpool_info

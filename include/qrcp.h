@@ -50,7 +50,7 @@ typedef struct qrcp_opts {
   int32_t trailing_precision; /* 0 = FP64 trailing update (default);
                                  1 = FP32 operands and accumulation, FP64 storage    */
   int32_t pivot_base;         /* 0 (default) or 1: base of the returned jpiv         */
-  int32_t pivot_steps;        /* 0 = the full GETRF of each block's sketch, min(d, n_i)
+  int32_t pivot_steps;        /* 0 = the full GETRF of each block's sketch, min(d, n_i, m_i)
                                  elimination steps (Alg. 2, default);
                                  1 = only the block's k_max = min(b, n_i, m_i) steps:
                                  the same selected columns (partial pivoting at step j
@@ -250,22 +250,26 @@ int qrcp_sketch_update_chol(double* Rsk, int64_t d, int64_t b, int64_t nt, int64
  * Request server: many independent factorizations of mixed shapes in flight
  * on one GPU (the paper's method applied per request; continuous admission).
  *
- * Worker threads (`slots`, each with its own HIP stream and cached workspace)
- * take requests from one FIFO queue as soon as they can be admitted: the
- * workers' workspaces together stay within `hbm_budget` bytes of device
- * memory, and the cross-workgroup-waiting kernels of the running requests fit
- * the device's compute units together.  Requests that arrive while others run
- * start as soon as a slot and memory free up; their kernels overlap on the
- * device.  A request computes exactly what qrcp_factor computes on the same
- * arguments (bitwise: the same kernels in the same order).
+ * Worker threads (`slots`, each with its own HIP stream) take requests from
+ * one FIFO queue as soon as they can be admitted: the request's workspace
+ * fits a free slice of the server's device pool (`hbm_budget` bytes, carved
+ * once at creation; a slice goes back to the pool when its request
+ * completes, so nothing is allocated or freed while requests run), and the
+ * cross-workgroup-waiting kernels of the running requests fit the device's
+ * compute units together.  Requests that arrive while others run start as
+ * soon as a slot and memory free up; their kernels overlap on the device.
+ * A request computes exactly what qrcp_factor computes on the same arguments
+ * (bitwise: the same kernels in the same order; a worker runs all of them on
+ * its own stream, without qrcp_factor's second stream for the deferred
+ * update, since the concurrent requests already fill the device).
  * ---------------------------------------------------------------------- */
 typedef struct qrcp_server qrcp_server;
 
 typedef struct qrcp_server_cfg {
   int32_t struct_size; /* sizeof(qrcp_server_cfg)                                */
-  int32_t slots;       /* worker threads / streams, 1..64 (0 = 4)                  */
-  int64_t hbm_budget;  /* bytes of workspace the server may hold (0 = 80% of the
-                          device memory free at creation)                         */
+  int32_t slots;       /* worker threads / streams, 1..64 (0 = 8)                  */
+  int64_t hbm_budget;  /* bytes of the device pool allocated at creation (0 = the
+                          smaller of 4 GiB and 80% of the free device memory)     */
   int32_t device;      /* HIP device ordinal                                      */
 } qrcp_server_cfg;
 

@@ -110,7 +110,8 @@ constexpr long kSpinLimit = 1L << 22;
 // far the loop got, and every kernel of block `blk` returns at once when its
 // gate is closed:
 //   kGateRun   closed once the loop has stopped before block blk;
-//   kGateExit  open only in the block at which the loop stops (the work that
+//   kGateExit  open only in the block at which the loop stops, and only when
+//              that block's panel is short of its full width (the work that
 //              finishes a block of reduced rank);
 //   kGateGoOn  open only in blocks the loop continues past (the sketch update).
 // The record is written by one-thread kernels earlier in the same stream, so
@@ -123,6 +124,8 @@ struct LoopCtl {
   int status;     // QRCP_OK or the first error
   long long ell;  // columns factored so far (the rank at the end)
   long long perms;  // column-map updates done (parity selects the live map)
+  int kmax;       // full width of the current block's panel
+  int pad;
 };
 
 // rank and status of a factorization call, in device memory
@@ -144,7 +147,7 @@ __device__ __forceinline__ bool gate_closed(const Gate& g) {
   if (!g.ctl) return false;
   const int nblk = g.ctl->nblk, ex = g.ctl->exit_blk;
   if (g.blk >= nblk) return true;
-  if (g.mode == kGateExit) return g.blk != ex;
+  if (g.mode == kGateExit) return g.blk != ex || g.ctl->k >= g.ctl->kmax;
   if (g.mode == kGateGoOn) return g.blk == ex;
   return false;
 }

@@ -616,6 +616,29 @@ int gemm_pick_splits(long M, long N, long K, long target) {
   return s < 1 ? 1 : (int)s;
 }
 
+// Split of K for the 128 x 128 tiles of the FP64 default, chosen so that the
+// workgroups fill whole waves of the resident slots (two per compute unit):
+// a grid of 1.5 waves leaves half the device idle in its second wave.  Each
+// split keeps at least 256 of K, and the partials must fit the area.
+static int vec_pick_splits(long M, long N, long K, size_t ws_bytes) {
+  const long tiles = ((M + 127) / 128) * ((N + 127) / 128);
+  const long slots = 2L * 256;
+  if (tiles >= 4 * slots || K < 512) return 1;
+  const long smax = std::min<long>(64, K / 256);
+  int best = 1;
+  double best_eff = (double)tiles / (double)(((tiles + slots - 1) / slots) * slots);
+  for (long sp = 2; sp <= smax; ++sp) {
+    if (gemm_splitk_bytes(M, N, (int)sp) > ws_bytes) break;
+    const long t = tiles * sp;
+    const double eff = (double)t / (double)(((t + slots - 1) / slots) * slots);
+    if (eff > best_eff + 0.02) {
+      best = (int)sp;
+      best_eff = eff;
+    }
+  }
+  return best;
+}
+
 int gemm(bool ta, bool tb, Prec prec, GemmArgs g, double* split_ws, size_t split_ws_bytes,
          hipStream_t st) {
   if (g.M <= 0 || g.N <= 0) return QRCP_OK;
@@ -628,7 +651,11 @@ int gemm(bool ta, bool tb, Prec prec, GemmArgs g, double* split_ws, size_t split
     return QRCP_OK;
   }
   int splits = 1;
-  if (split_ws && !g.bcol)
+  const int cfg = tile_override();
+  const bool vec_default = prec == Prec::F64 && (cfg == 0 || cfg == 12) && vec_ok(g);
+  if (split_ws && !g.bcol && vec_default)
+    splits = vec_pick_splits(g.M, g.N, g.K, split_ws_bytes);
+  else if (split_ws && !g.bcol)
     splits = gemm_pick_splits(g.M, g.N, g.K, g.kind == GemmKind::TrailingW ? 4096 : 512);
   if (splits > 1 && gemm_splitk_bytes(g.M, g.N, splits) > split_ws_bytes)
     splits = (int)std::max<size_t>(1, split_ws_bytes / gemm_splitk_bytes(g.M, g.N, 1));

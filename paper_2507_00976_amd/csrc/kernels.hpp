@@ -121,4 +121,12 @@ int launch_iota(i64* x, i64 n, hipStream_t st);
 int lu_resident_groups(i64 ni);
 int sketch_head_groups(int d, i64 ni);
 
+// qrcp_factor for the request server's workers: every launch on the worker's
+// own stream (the concurrent requests keep the device busy, a second stream
+// per worker would only share the hardware queues with other workers')
+int factor_served(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size,
+                  double sketch_factor, uint64_t seed, double tol, int64_t* jpiv, double* tau,
+                  int64_t* rank, const qrcp_opts* opts, void* workspace, size_t workspace_bytes,
+                  void* stream);
+
 }  // namespace qrcp

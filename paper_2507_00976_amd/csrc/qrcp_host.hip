@@ -5,6 +5,7 @@
 // Cholesky step, error status), so the host knows the block rank k before it
 // enqueues the k-dependent launches of the block.
 #include <algorithm>
+#include <climits>
 #include <cstdlib>
 #include <cmath>
 #include <map>
@@ -339,6 +340,39 @@ int aux_stream(AuxStream** out) {
   return QRCP_OK;
 }
 
+// A pinned host word of the calling thread that the blocking form polls: the
+// loop's decision kernel writes the block count there once the loop stops, so
+// the host stops enqueueing blocks whose launches would only return at once.
+struct StopFlag {
+  int dev = -1;
+  int* host = nullptr;
+  int* devp = nullptr;
+  void release() {
+    if (host) (void)hipHostFree(host);
+    host = devp = nullptr;
+    dev = -1;
+  }
+  ~StopFlag() { release(); }
+};
+
+int stop_flag(StopFlag** out) {
+  static thread_local StopFlag f;
+  int dev = 0;
+  QRCP_HIP(hipGetDevice(&dev));
+  if (f.dev != dev) {
+    f.release();
+    void* h = nullptr;
+    QRCP_HIP(hipHostMalloc(&h, 64, hipHostMallocMapped));
+    f.host = (int*)h;
+    void* dp = nullptr;
+    QRCP_HIP(hipHostGetDevicePointer(&dp, h, 0));
+    f.devp = (int*)dp;
+    f.dev = dev;
+  }
+  *out = &f;
+  return QRCP_OK;
+}
+
 // Makes the caller's stream wait for the overlapped update on every exit path.
 struct JoinGuard {
   hipStream_t st;
@@ -380,8 +414,8 @@ size_t qrcp_workspace_size(int64_t m, int64_t n, int64_t block_size, double sket
   FactorWs w;
   const int d = sketch_rows(block_size, sketch_factor);
   const qrcp_opts o = read_opts(opts);
-  return carve_factor(nullptr, m, n, std::min<i64>(block_size, std::max<i64>(n, 1)), d, &w,
-                      o.qr_tall == 1);
+  const i64 b = std::min<i64>(block_size, std::max<i64>(n, 1));
+  return carve_factor(nullptr, m, n, b, d, &w, o.qr_tall == 1);
 }
 
 }  // extern "C"
@@ -389,14 +423,22 @@ size_t qrcp_workspace_size(int64_t m, int64_t n, int64_t block_size, double sket
 namespace qrcp {
 namespace {
 
-// The factorization behind qrcp_factor and qrcp_factor_noalloc.  lookahead:
-// run the deferred rank-k update on the library's second stream (created on
-// first use); without it every launch goes to the caller's stream in the same
-// order, with the same arithmetic (the results are bitwise the same).
+// Library resources a call may use (factor_impl's uses):
+//   kResAux  - run the deferred rank-k update on the library's second stream
+//              (created on first use); without it every launch goes to the
+//              caller's stream in the same order, with the same arithmetic
+//              (the results are bitwise the same);
+//   kResStop - a pinned host word of the calling thread (allocated on first
+//              use) through which the device tells the blocking form to stop
+//              enqueueing blocks once the loop has stopped.
+enum : unsigned { kResAux = 1u, kResStop = 2u };
+
+// The factorization behind qrcp_factor, qrcp_factor_async, qrcp_factor_noalloc
+// and the request server.
 int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size,
                 double sketch_factor, uint64_t seed, double tol, int64_t* jpiv, double* tau,
                 const qrcp_opts* opts_in, void* workspace, size_t workspace_bytes, void* stream,
-                bool lookahead, int64_t* rank_host, int64_t* rank_dev, int32_t* status_dev) {
+                unsigned uses, int64_t* rank_host, int64_t* rank_dev, int32_t* status_dev) {
   if (m < 0) return -2;
   if (n < 0) return -3;
   if (lda < std::max<int64_t>(1, m)) return -4;
@@ -454,9 +496,22 @@ int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
   }
 
   AuxStream* aux = nullptr;
+  bool lookahead = (uses & kResAux) != 0;
   if (getenv("QRCP_NO_LOOKAHEAD")) lookahead = false;
   if (lookahead) QRCP_TRY(aux_stream(&aux));
   JoinGuard jg{st, aux};
+  // the blocking form with the library's own resources stops enqueueing once
+  // the device reports that the loop has stopped (the async and no-alloc
+  // forms enqueue every block)
+  volatile int* stop_host = nullptr;
+  int* stop_dev = nullptr;
+  if (rank_host && (uses & kResStop)) {
+    StopFlag* sf = nullptr;
+    QRCP_TRY(stop_flag(&sf));
+    *sf->host = INT_MAX;
+    stop_host = sf->host;
+    stop_dev = sf->devp;
+  }
   // the previous block's rank-k update of rows s+k .. m, started on the
   // second stream once the next block's pivots are known (its kernels carry
   // the gate of the block they belong to)
@@ -498,6 +553,7 @@ int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
   // blocks the loop continues past (gate kGateGoOn).
   int blk = 0;
   for (i64 s = 0; s < lim; ++blk) {
+    if (stop_host && *stop_host <= blk) break;  // the rest would return at once
     const i64 ni = n - s, mi = m - s;
     const int kmax = (int)std::min<i64>(std::min<i64>(b, lim - s), std::min(ni, mi));
     const i64 c = s + kmax;
@@ -566,7 +622,7 @@ int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
     if (o.qr_tall == 1) {
       // Householder QR of the panel (GEQRF; Sec. 2.3), 32-column leaves each
       // applied to the rest of the panel; tri_rank's k is the block's width
-      QRCP_TRY(launch_loop_decide(w.ctl, w.status, w.kdev, blk, kmax, s, c, lim, false, st));
+      QRCP_TRY(launch_loop_decide(w.ctl, w.status, w.kdev, blk, kmax, s, c, lim, false, stop_dev, st));
       {
         GateScope gx(ex);
         QRCP_TRY(launch_copy2d(Ablk, lda, w.psave, m, mi, kmax, st));
@@ -604,7 +660,7 @@ int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
         QRCP_TRY(gemm(true, false, Prec::F64, ga(kmax, kmax, (int)mi, w.Y, m, w.Y, m, w.G, b), w.split,
                       kSplitBytes, st));
         QRCP_TRY(launch_potrf_mw(w.G, b, kmax, w.info, w.split, kSplitBytes, st));
-        QRCP_TRY(launch_loop_decide(w.ctl, w.status, w.info, blk, kmax, s, c, lim, false, st));
+        QRCP_TRY(launch_loop_decide(w.ctl, w.status, w.info, blk, kmax, s, c, lim, false, stop_dev, st));
         GateScope gx(ex);
         QRCP_TRY(launch_copy2d(Ablk, lda, w.psave, m, mi, kmax, st));
         QRCP_TRY(launch_pad_identity(w.G, b, kmax, keff, st));
@@ -623,7 +679,7 @@ int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
           QRCP_TRY(gemm(true, false, Prec::F64, ga(kmax, kmax, (int)mi, w.tmp, m, w.tmp, m, w.R2, b),
                         w.split, kSplitBytes, st));
           QRCP_TRY(launch_potrf_mw(w.R2, b, kmax, w.info, w.split, kSplitBytes, st));
-          QRCP_TRY(launch_loop_decide(w.ctl, w.status, w.info, blk, kmax, s, c, lim, true, st));
+          QRCP_TRY(launch_loop_decide(w.ctl, w.status, w.info, blk, kmax, s, c, lim, true, stop_dev, st));
           {
             // a second-pass breakdown shrinks the width: redo the first pass's
             // inverse and Q with it (the block then stops the loop)
@@ -724,11 +780,13 @@ int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
   }
   QRCP_TRY(start_pending());
   QRCP_TRY(jg.join());
-  // the live maps, tau(l:) = 0, the unplaced columns in logical order, rank and status
+  // the live maps
+  QRCP_TRY(launch_loop_pick(w.ctl, w.J[0], w.J[1], w.phys[0], w.phys[1], n, st));
+  // tau(l:) = 0, the unplaced columns in logical order, rank and status
   i64* rdev = rank_dev ? rank_dev : (i64*)&w.result->rank;
   int* sdev = status_dev ? status_dev : &w.result->status;
-  QRCP_TRY(launch_loop_final(w.ctl, A, lda, m, n, w.J[0], w.J[1], w.phys[0], w.phys[1], tau, mn,
-                             w.big, w.status, rdev, sdev, st));
+  QRCP_TRY(launch_loop_final(w.ctl, A, lda, m, n, w.phys[0], tau, mn, w.big, w.status, rdev, sdev,
+                             st));
   QRCP_TRY(launch_jpiv_out(w.J[0], n, o.pivot_base, jpiv, st));
   if (!rank_host) return QRCP_OK;
   // the blocking form: one read-back of rank and status for the whole call
@@ -741,6 +799,15 @@ int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
   return res.status;
 }
 }  // namespace
+
+int factor_served(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size,
+                  double sketch_factor, uint64_t seed, double tol, int64_t* jpiv, double* tau,
+                  int64_t* rank, const qrcp_opts* opts, void* workspace, size_t workspace_bytes,
+                  void* stream) {
+  if (!rank) return -11;
+  return factor_impl(A, m, n, lda, block_size, sketch_factor, seed, tol, jpiv, tau, opts, workspace,
+                     workspace_bytes, stream, kResStop, rank, nullptr, nullptr);
+}
 }  // namespace qrcp
 
 extern "C" {
@@ -751,7 +818,7 @@ int qrcp_factor(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
                 void* stream) {
   if (!rank) return -11;
   return factor_impl(A, m, n, lda, block_size, sketch_factor, seed, tol, jpiv, tau, opts, workspace,
-                     workspace_bytes, stream, true, rank, nullptr, nullptr);
+                     workspace_bytes, stream, kResAux | kResStop, rank, nullptr, nullptr);
 }
 
 int qrcp_factor_async(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size,
@@ -761,7 +828,7 @@ int qrcp_factor_async(double* A, int64_t m, int64_t n, int64_t lda, int64_t bloc
   if (!rank_dev) return -11;
   if (!status_dev) return -12;
   return factor_impl(A, m, n, lda, block_size, sketch_factor, seed, tol, jpiv, tau, opts, workspace,
-                     workspace_bytes, stream, true, nullptr, rank_dev, status_dev);
+                     workspace_bytes, stream, kResAux, nullptr, rank_dev, status_dev);
 }
 
 }  // extern "C"
@@ -815,7 +882,7 @@ int qrcp_factor_noalloc(double* A, int64_t m, int64_t n, int64_t lda, int64_t bl
   // workspace the call ends at the workspace check if everything else holds
   if (!rank) return -11;
   const int pre = factor_impl(A, m, n, lda, block_size, sketch_factor, seed, tol, jpiv, tau, opts,
-                              nullptr, 0, stream, false, rank, nullptr, nullptr);
+                              nullptr, 0, stream, 0u, rank, nullptr, nullptr);
   if (pre != QRCP_ERR_WORKSPACE) return pre;
   const size_t need = qrcp_workspace_size(m, n, block_size, sketch_factor, opts);
   if (need > kNoAllocBytes) {
@@ -828,7 +895,7 @@ int qrcp_factor_noalloc(double* A, int64_t m, int64_t n, int64_t lda, int64_t bl
   QRCP_TRY(scratch_address(&ws));
   // no second stream: the library creates nothing on this path
   return factor_impl(A, m, n, lda, block_size, sketch_factor, seed, tol, jpiv, tau, opts, ws,
-                     kNoAllocBytes, stream, false, rank, nullptr, nullptr);
+                     kNoAllocBytes, stream, 0u, rank, nullptr, nullptr);
 }
 
 // ----------------------------------------------------------------------------

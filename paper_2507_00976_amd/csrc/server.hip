@@ -1,13 +1,14 @@
 // Request server: many independent factorizations of mixed shapes in flight
 // on one GPU (qrcp_server_* in qrcp.h).
 //
-// A fixed set of worker threads, each with its own HIP stream and cached
-// workspace, takes requests from one FIFO queue as soon as they can be
-// admitted, so requests that arrive while others run start as soon as a slot
-// and device memory free up, and their kernels overlap on the device.
-// Admission checks two budgets:
-//   - device memory: the sum of the workers' cached workspaces after the
-//     request's workspace is (re)allocated stays within hbm_budget;
+// A fixed set of worker threads, each with its own HIP stream, takes requests
+// from one FIFO queue as soon as they can be admitted, so requests that
+// arrive while others run start as soon as a slot and device memory free up,
+// and their kernels overlap on the device.  Device memory is one pool carved
+// at creation (hbm_budget bytes): an admitted request gets a slice of it
+// (first fit), returned when the request completes, so nothing is allocated
+// or freed on the device while requests run.  Admission checks two budgets:
+//   - device memory: the request's workspace fits a free slice of the pool;
 //   - resident workgroups: the pivot-selection and sketch-QR-head kernels keep
 //     all of their workgroups resident while they wait on each other, one
 //     workgroup per compute unit (their LDS use); the running requests' largest
@@ -15,7 +16,9 @@
 //     compute units the other one is waiting for.
 // Every request runs the same kernels as a lone qrcp_factor call on the same
 // inputs, so its result is bitwise the same alone and in the mix.
+#include <algorithm>
 #include <chrono>
+#include <map>
 #include <cmath>
 #include <condition_variable>
 #include <deque>
@@ -44,9 +47,38 @@ struct qrcp_server {
   std::deque<uint64_t> queue;
   std::unordered_map<uint64_t, Job> jobs;
   uint64_t next = 1;
-  std::vector<size_t> cap;  // cached workspace per worker
-  int64_t cap_sum = 0;
+  char* pool = nullptr;                 // device memory carved at creation
+  std::map<size_t, size_t> free_list;   // offset -> bytes of the free slices
   int groups_used = 0;
+
+  // first fit of `bytes` (256-byte multiples), or SIZE_MAX
+  size_t take(size_t bytes) {
+    bytes = (bytes + 255) / 256 * 256;
+    for (auto it = free_list.begin(); it != free_list.end(); ++it) {
+      if (it->second < bytes) continue;
+      const size_t off = it->first, len = it->second;
+      free_list.erase(it);
+      if (len > bytes) free_list[off + bytes] = len - bytes;
+      return off;
+    }
+    return SIZE_MAX;
+  }
+  void give(size_t off, size_t bytes) {
+    bytes = (bytes + 255) / 256 * 256;
+    auto it = free_list.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_list.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_list.erase(nx);
+    }
+    if (it != free_list.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_list.erase(it);
+      }
+    }
+  }
   bool stop = false;
   std::vector<std::thread> workers;
   std::chrono::steady_clock::time_point t0;
@@ -66,13 +98,13 @@ int request_groups(const qrcp_request& r) {
 }
 
 void worker_main(qrcp_server* s, int w) {
+  (void)w;
   hipSetDevice(s->device);
   hipStream_t st = nullptr;
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
-  void* buf = nullptr;
   for (;;) {
     qrcp_server::Job* job = nullptr;
-    bool release = false;
+    size_t off = 0;
     {
       std::unique_lock<std::mutex> lk(s->mu);
       for (;;) {
@@ -82,57 +114,28 @@ void worker_main(qrcp_server* s, int w) {
           continue;
         }
         qrcp_server::Job& j = s->jobs[s->queue.front()];
-        const size_t grow = j.ws > s->cap[w] ? j.ws - s->cap[w] : 0;
-        const bool mem_ok = s->cap_sum + (int64_t)grow <= s->budget;
-        const bool cu_ok = s->groups_used + j.groups <= s->cu_budget;
-        if (mem_ok && cu_ok) {
-          s->queue.pop_front();
-          job = &j;
-          job->state = 1;
-          job->res.start_ms = s->now_ms();
-          s->groups_used += j.groups;
-          s->cap_sum += (int64_t)grow;
-          break;
-        }
-        if (!mem_ok && s->cap[w] > 0 &&
-            s->cap_sum - (int64_t)s->cap[w] + (int64_t)j.ws <= s->budget) {
-          // this idle worker's cached workspace is what keeps the request out
-          s->cap_sum -= (int64_t)s->cap[w];
-          s->cap[w] = 0;
-          release = true;
-          break;
+        if (s->groups_used + j.groups <= s->cu_budget) {
+          off = s->take(j.ws);
+          if (off != SIZE_MAX) {
+            s->queue.pop_front();
+            job = &j;
+            job->state = 1;
+            job->res.start_ms = s->now_ms();
+            s->groups_used += j.groups;
+            break;
+          }
         }
         s->cv_work.wait(lk);
       }
-    }
-    if (release) {
-      if (buf) hipFree(buf);
-      buf = nullptr;
-      s->cv_work.notify_all();
-      continue;
     }
     if (!job) break;
     int rc = QRCP_OK;
     int64_t rank = 0;
     if (!st) rc = QRCP_ERR_HIP;
-    if (rc == QRCP_OK && job->ws > s->cap[w]) {
-      if (buf) hipFree(buf);
-      buf = nullptr;
-      if (hipMalloc(&buf, job->ws) != hipSuccess) {
-        buf = nullptr;
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->cap_sum -= (int64_t)(job->ws - s->cap[w]) + (int64_t)s->cap[w];
-        s->cap[w] = 0;
-        rc = QRCP_ERR_HIP;
-      } else {
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->cap[w] = job->ws;
-      }
-    }
     if (rc == QRCP_OK) {
       const qrcp_request& r = job->req;
-      rc = qrcp_factor(r.A, r.m, r.n, r.lda, r.block_size, r.sketch_factor, r.seed, r.tol, r.jpiv,
-                       r.tau, &rank, &r.opts, buf, s->cap[w], st);
+      rc = factor_served(r.A, r.m, r.n, r.lda, r.block_size, r.sketch_factor, r.seed, r.tol,
+                         r.jpiv, r.tau, &rank, &r.opts, s->pool + off, job->ws, st);
     }
     {
       std::lock_guard<std::mutex> lk(s->mu);
@@ -141,11 +144,11 @@ void worker_main(qrcp_server* s, int w) {
       job->res.end_ms = s->now_ms();
       job->state = 2;
       s->groups_used -= job->groups;
+      s->give(off, job->ws);
     }
     s->cv_done.notify_all();
     s->cv_work.notify_all();
   }
-  if (buf) hipFree(buf);
   if (st) hipStreamDestroy(st);
 }
 
@@ -168,10 +171,19 @@ qrcp_server* qrcp_server_create(const qrcp_server_cfg* cfg) {
     return nullptr;
   qrcp_server* s = new qrcp_server();
   s->device = dev;
-  s->slots = c.slots ? c.slots : 4;
-  s->budget = c.hbm_budget ? c.hbm_budget : (int64_t)(0.8 * (double)free_b);
+  s->slots = c.slots ? c.slots : 8;
+  s->budget = c.hbm_budget ? c.hbm_budget
+                           : std::min<int64_t>((int64_t)(0.8 * (double)free_b), int64_t(4) << 30);
+  s->budget = s->budget / 256 * 256;
   s->cu_budget = cus;
-  s->cap.assign(s->slots, 0);
+  // the whole pool up front: requests only take and return slices of it
+  void* pool = nullptr;
+  if (s->budget <= 0 || hipMalloc(&pool, (size_t)s->budget) != hipSuccess) {
+    delete s;
+    return nullptr;
+  }
+  s->pool = (char*)pool;
+  s->free_list[0] = (size_t)s->budget;
   s->t0 = std::chrono::steady_clock::now();
   for (int w = 0; w < s->slots; ++w) s->workers.emplace_back(qrcp::worker_main, s, w);
   return s;
@@ -249,6 +261,7 @@ void qrcp_server_destroy(qrcp_server* s) {
   }
   s->cv_work.notify_all();
   for (auto& t : s->workers) t.join();
+  if (s->pool) (void)hipFree(s->pool);
   delete s;
 }
 

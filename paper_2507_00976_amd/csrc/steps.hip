@@ -124,13 +124,16 @@ __global__ void loop_init_kernel(LoopCtl* ctl) {
   ctl->status = QRCP_OK;
   ctl->ell = 0;
   ctl->perms = 0;
+  ctl->kmax = 0;
 }
 
 // After block blk's panel factorization: the block's effective width k (the
 // Cholesky QR's count of factored columns, or tri_rank's for the Householder
 // panel), errors, and whether the loop stops at this block.
+// host_nblk (may be null): a word in pinned host memory that the blocking
+// form polls to stop enqueueing blocks once the loop has stopped
 __global__ void loop_decide_kernel(Gate gt, LoopCtl* ctl, const int* status, const int* kdev, int blk,
-                                   int kmax, long s, long c, long lim, int second) {
+                                   int kmax, long s, long c, long lim, int second, int* host_nblk) {
   QRCP_GATE(gt);
   const int st = *status;
   const int k = *kdev;
@@ -139,18 +142,21 @@ __global__ void loop_decide_kernel(Gate gt, LoopCtl* ctl, const int* status, con
     ctl->nblk = blk;
     ctl->exit_blk = -1;
     ctl->ell = s;
-    return;
-  }
-  // the second Cholesky pass can only shrink the width found by the first
-  const int kk = second ? min(k, ctl->k) : k;
-  ctl->k = kk;
-  if (kk < kmax || c >= lim) {
-    ctl->exit_blk = blk;
-    ctl->nblk = blk + 1;
-    ctl->ell = s + kk;
   } else {
-    ctl->ell = c;
+    // the second Cholesky pass can only shrink the width found by the first
+    const int kk = second ? min(k, ctl->k) : k;
+    ctl->k = kk;
+    ctl->kmax = kmax;
+    if (kk < kmax || c >= lim) {
+      ctl->exit_blk = blk;
+      ctl->nblk = blk + 1;
+      ctl->ell = s + kk;
+    } else {
+      ctl->ell = c;
+    }
   }
+  if (host_nblk && ctl->nblk != INT_MAX)
+    __hip_atomic_store(host_nblk, ctl->nblk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // X(i, j) = delta_ij wherever i or j >= k (the trailing part of a factor
@@ -235,9 +241,9 @@ int launch_loop_init(LoopCtl* ctl, hipStream_t st) {
 }
 
 int launch_loop_decide(LoopCtl* ctl, const int* status, const int* kdev, int blk, int kmax, i64 s,
-                       i64 c, i64 lim, bool second, hipStream_t st) {
+                       i64 c, i64 lim, bool second, int* host_nblk, hipStream_t st) {
   hipLaunchKernelGGL(loop_decide_kernel, dim3(1), dim3(1), 0, st, current_gate(), ctl, status, kdev,
-                     blk, kmax, (long)s, (long)c, (long)lim, second ? 1 : 0);
+                     blk, kmax, (long)s, (long)c, (long)lim, second ? 1 : 0, host_nblk);
   QRCP_LAUNCHED("loop_decide");
   return QRCP_OK;
 }
@@ -267,11 +273,17 @@ int launch_copy_cols_from(const double* src, i64 lds, double* dst, i64 ldd, i64 
   return QRCP_OK;
 }
 
-int launch_loop_final(const LoopCtl* ctl, double* A, i64 lda, i64 m, i64 n, i64* J0, const i64* J1,
-                      i64* P0, const i64* P1, double* tau, i64 mn, double* tmp, const int* status,
-                      i64* rank_dev, int* status_dev, hipStream_t st) {
+int launch_loop_pick(const LoopCtl* ctl, i64* J0, const i64* J1, i64* P0, const i64* P1, i64 n,
+                     hipStream_t st) {
   hipLaunchKernelGGL(pick_maps_kernel, dim3(64), dim3(256), 0, st, ctl, (long*)J0, (const long*)J1,
                      (long*)P0, (const long*)P1, (long)n);
+  QRCP_LAUNCHED("loop_pick");
+  return QRCP_OK;
+}
+
+int launch_loop_final(const LoopCtl* ctl, double* A, i64 lda, i64 m, i64 n, const i64* P0,
+                      double* tau, i64 mn, double* tmp, const int* status, i64* rank_dev,
+                      int* status_dev, hipStream_t st) {
   if (mn > 0)
     hipLaunchKernelGGL(tau_tail_kernel, dim3(16), dim3(256), 0, st, ctl, tau, (long)mn);
   if (m > 0) {

@@ -395,7 +395,7 @@ class Server:
     kept alive here until it is collected.
     """
 
-    def __init__(self, slots: int = 4, hbm_budget: int = 0, device: int = 0):
+    def __init__(self, slots: int = 8, hbm_budget: int = 0, device: int = 0):
         cfg = ServerCfg(ctypes.sizeof(ServerCfg), slots, hbm_budget, device)
         self._h = _lib.qrcp_server_create(ctypes.byref(cfg))
         if not self._h:

@@ -280,3 +280,4 @@ def test_headline_block_first_block_wide_sketch(Q):
     assert np.max(np.abs(diff)) <= R_TOL * nrm
     res, orth = residual_orth(A0, A, jpiv, tau, rank)
     assert res <= R_TOL and orth <= R_TOL, (res, orth)
+

@@ -164,12 +164,23 @@ def test_kahan_pivot_quality(Q, qr_tall):
     sig = np.linalg.svd(a, compute_uv=False)
     ref = O.bqrrp(a, b, 1.25, 42, 0.0, qr_tall="geqrf" if qr_tall else "cholqr")
     got = run_gpu(Q, a, b, 1.25, 42, 0.0, qr_tall=qr_tall)
-    assert got.rank == ref.rank == n
     assert ref.min_margin() >= 1e-8
-    assert np.array_equal(got.jpiv, ref.jpiv)
     nrm = np.linalg.norm(a)
-    assert np.max(np.abs(np.triu(got.a) - np.triu(ref.a))) <= R_TOL * nrm
+    if qr_tall:
+        assert got.rank == ref.rank == n
+        assert np.array_equal(got.jpiv, ref.jpiv)
+        assert np.max(np.abs(np.triu(got.a) - np.triu(ref.a))) <= R_TOL * nrm
+    else:
+        # the last singular values lie far below eps ||A||: whether Cholesky QR
+        # of the last panel breaks down on its final column is decided by
+        # rounding (Alg. 3 squares the condition number), so the rank is n or
+        # n - 1 on either side; the selected columns agree up to there
+        assert ref.rank >= n - 1 and got.rank >= n - 1
+        l = min(got.rank, ref.rank)
+        assert np.array_equal(got.jpiv[:l], ref.jpiv[:l])
+        assert np.max(np.abs(np.triu(got.a[:l]) - np.triu(ref.a[:l]))) <= R_TOL * nrm
     live = sig >= 1e3 * np.finfo(float).eps * sig[0]
+    live[got.rank:] = False
     ratio = np.abs(np.diag(got.a))[live] / sig[live]
     assert ratio.min() >= 1e-2 and ratio.max() <= 1e2, (ratio.min(), ratio.max())
     _, rg, _ = sl.qr(a, pivoting=True)
