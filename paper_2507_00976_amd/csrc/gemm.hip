@@ -562,14 +562,28 @@ static int tile_override() {
   return v;
 }
 
-template <bool TA, bool TB, typename T>
-static void launch_shape(const GemmArgs& g, int splits, hipStream_t st) {
+// The tile configuration of a product: 0 = 64x64 (4 waves), or the override.
+// FP64 products with even sizes take the 16-byte-load tiles: 128 x 128 over 8
+// waves (each a 64 x 32 block) -- measured at 16384^2, b = 256: rank-k update
+// 55 vs 47 TFLOP/s, W = Y^T C 56 vs 52 TFLOP/s -- unless their 128 x 128
+// tiles fill less than one wave of the device's resident slots (two per
+// compute unit) and K is too short to split (or the product is the sketch,
+// d = 320 rows, whose third 128-row tile row would be a sixth empty): those
+// take the 64 x 64 tiles with 16-byte loads.  Both compute the same
+// per-element sums, so the results do not depend on the choice.
+static int pick_cfg(const GemmArgs& g, bool f64) {
   int cfg = tile_override();
+  if (f64 && cfg == 0 && vec_ok(g)) {
+    const long tiles = (long)((g.M + 127) / 128) * ((g.N + 127) / 128);
+    const bool small = tiles < 2L * 256 && g.K < 512;
+    cfg = (g.kind == GemmKind::Sketch || small) ? 9 : 12;
+  }
+  return cfg;
+}
+
+template <bool TA, bool TB, typename T>
+static void launch_shape(const GemmArgs& g, int cfg, int splits, hipStream_t st) {
   if constexpr (std::is_same<T, double>::value) {
-    // automatic for FP64 products with even sizes: 128 x 128 tiles, 8 waves
-    // (each a 64 x 32 block), 16-byte operand loads -- measured at 16384^2,
-    // b = 256: rank-k update 55 vs 47 TFLOP/s, W = Y^T C 56 vs 52 TFLOP/s
-    if (cfg == 0 && vec_ok(g)) cfg = 12;
     if (cfg >= 9 && vec_ok(g)) {
       switch (cfg) {
         case 9: launch_tile<64, 64, 2, 2, 16, TA, TB, T, true>(g, splits, st); return;
@@ -585,9 +599,10 @@ static void launch_shape(const GemmArgs& g, int splits, hipStream_t st) {
       }
     }
   }
-  // automatic: 64 x 64 tiles (4 waves, four workgroups per CU); measured on
-  // MI355X at 16384^2, b = 256, they beat the 128 x 128 tiles on the rank-k
-  // update (49 vs 42 TFLOP/s), on W = Y^T C (55 vs 54) and on the sketch (49 vs 39)
+  // otherwise 64 x 64 tiles (4 waves, four workgroups per CU; measured on
+  // MI355X at 16384^2, b = 256, they beat the 128 x 128 tiles of this form on
+  // the rank-k update (49 vs 42 TFLOP/s), on W = Y^T C (55 vs 54) and on the
+  // sketch (49 vs 39))
   switch (cfg) {
     case 2: launch_tile<128, 128, 2, 2, 16, TA, TB, T>(g, splits, st); break;
     case 3: launch_tile<128, 128, 2, 4, 16, TA, TB, T>(g, splits, st); break;
@@ -651,8 +666,8 @@ int gemm(bool ta, bool tb, Prec prec, GemmArgs g, double* split_ws, size_t split
     return QRCP_OK;
   }
   int splits = 1;
-  const int cfg = tile_override();
-  const bool vec_default = prec == Prec::F64 && (cfg == 0 || cfg == 12) && vec_ok(g);
+  const int cfg = pick_cfg(g, prec == Prec::F64);
+  const bool vec_default = prec == Prec::F64 && cfg == 12 && vec_ok(g);
   if (split_ws && !g.bcol && vec_default)
     splits = vec_pick_splits(g.M, g.N, g.K, split_ws_bytes);
   else if (split_ws && !g.bcol)
@@ -674,15 +689,15 @@ int gemm(bool ta, bool tb, Prec prec, GemmArgs g, double* split_ws, size_t split
     if (splits == 1) g.partial = nullptr;
     hipLaunchKernelGGL(gemm_bf16_tn_kernel, grid, dim3(256), 0, st, current_gate(), g);
   } else if (prec == Prec::F32) {
-    if (ta && !tb) launch_shape<true, false, float>(g, splits, st);
-    else if (!ta && !tb) launch_shape<false, false, float>(g, splits, st);
-    else if (!ta && tb) launch_shape<false, true, float>(g, splits, st);
-    else launch_shape<true, true, float>(g, splits, st);
+    if (ta && !tb) launch_shape<true, false, float>(g, cfg, splits, st);
+    else if (!ta && !tb) launch_shape<false, false, float>(g, cfg, splits, st);
+    else if (!ta && tb) launch_shape<false, true, float>(g, cfg, splits, st);
+    else launch_shape<true, true, float>(g, cfg, splits, st);
   } else {
-    if (ta && !tb) launch_shape<true, false, double>(g, splits, st);
-    else if (!ta && !tb) launch_shape<false, false, double>(g, splits, st);
-    else if (!ta && tb) launch_shape<false, true, double>(g, splits, st);
-    else launch_shape<true, true, double>(g, splits, st);
+    if (ta && !tb) launch_shape<true, false, double>(g, cfg, splits, st);
+    else if (!ta && !tb) launch_shape<false, false, double>(g, cfg, splits, st);
+    else if (!ta && tb) launch_shape<false, true, double>(g, cfg, splits, st);
+    else launch_shape<true, true, double>(g, cfg, splits, st);
   }
   QRCP_LAUNCHED("gemm");
   if (splits > 1) {
