@@ -24,7 +24,9 @@
 // position and row id, x, the candidate's multiplier for the previous pivot,
 // its value in the next column) and a payload (its panel row).  Every
 // workgroup reads all headers and agrees on the winner (largest |x|, ties to
-// the smallest current position, as IDAMAX).  The header alone is enough to
+// the smallest current position, as IDAMAX).  A step's headers are stored
+// word-major (word w of every workgroup contiguous), so a wave reading the
+// headers of 64 workgroups touches 8 cache lines per word instead of 64.  The header alone is enough to
 // eliminate in the next column at once; the previous pivot's contribution to
 // the remaining panel columns is applied one step late, from the previous
 // winner's payload, which was fetched while the current headers travelled
@@ -47,7 +49,6 @@ namespace {
 constexpr int NB = 32;    // panel width
 constexpr int NT = 256;   // threads per workgroup
 constexpr int HW = 5;     // header words
-constexpr int RW = 40;    // words per record: header, NB payload words, padding
 constexpr int TCH = 256;  // trailing columns per chunk
 constexpr uint64_t SENT = 0xFFF0DEADBEEFCAFEull;
 constexpr uint64_t NOCAND = 0x7FFFFFFF00000000ull;
@@ -66,11 +67,22 @@ struct LuArgs {
   long ni;
   int steps;         // elimination steps: at most min(d, ni)
   double* xw;        // ni x d row-major working copy
-  uint64_t* rec;     // steps x G x RW words, sentinel-filled
+  uint64_t* rec;     // steps x step_words(G) words, sentinel-filled
   long* ipiv;
   long* jsk;
   int* status;
 };
+
+// Records of one step: HW header words of each of G workgroups, word-major
+// with rows of gpad(G) words (64-byte lines), then G payloads of NB words.
+__host__ __device__ constexpr long gpad(int G) { return (G + 7) & ~7; }
+__host__ __device__ constexpr long step_words(int G) { return HW * gpad(G) + (long)G * NB; }
+__device__ __forceinline__ uint64_t* hdr_at(uint64_t* rec, long j, int G, int g) {
+  return rec + j * step_words(G) + g;  // word w at + w * gpad(G)
+}
+__device__ __forceinline__ uint64_t* pay_at(uint64_t* rec, long j, int G, int g) {
+  return rec + j * step_words(G) + HW * gpad(G) + (long)g * NB;
+}
 
 __device__ __forceinline__ bool better(double va, uint64_t ka, double vb, uint64_t kb) {
   return va > vb || (va == vb && ka < kb);
@@ -221,6 +233,7 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(Gate gt, LuArgs a) {
   const long ni = a.ni;
   const int steps = a.steps;
   const long row0 = (long)g * R;
+  const long hs = gpad(G);  // stride between a step's header words
 
   // working copy of this workgroup's rows + non-finite check
   if (tid == 0) {
@@ -331,7 +344,7 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(Gate gt, LuArgs a) {
           if (lane == 2) word = w2;
           if (lane == 3) word = w3;
           if (lane == 4) word = w4;
-          store_agent(a.rec + ((long)j * G + g) * RW + lane, word);
+          store_agent(hdr_at(a.rec, j, G, g) + lane * gpad(G), word);
         }
         return olr;
       };
@@ -351,7 +364,7 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(Gate gt, LuArgs a) {
         wave_lds_sync();
         if (lane < NB) {
           const double v = (lane < jl) ? sLr[par][olr][lane] : sCand[lane - jl];
-          store_agent(a.rec + ((long)j * G + g) * RW + HW + lane, canon(v));
+          store_agent(pay_at(a.rec, j, G, g) + lane, canon(v));
         }
       };
 
@@ -371,9 +384,9 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(Gate gt, LuArgs a) {
         for (int qq = 0; qq < GQ; ++qq) {
           const int gg = lane + 64 * qq;
           if (gg < G && !to) {
-            uint64_t* r = a.rec + ((long)j * G + gg) * RW;
+            uint64_t* r = hdr_at(a.rec, j, G, gg);
 #pragma unroll
-            for (int i = 0; i < HW; ++i) hdr[qq][i] = load_agent(r + i);
+            for (int i = 0; i < HW; ++i) hdr[qq][i] = load_agent(r + i * hs);
           }
         }
 #pragma unroll
@@ -383,7 +396,7 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(Gate gt, LuArgs a) {
           hr[qq] = 0.0;
           const int gg = lane + 64 * qq;
           if (gg < G && !to) {
-            uint64_t* r = a.rec + ((long)j * G + gg) * RW;
+            uint64_t* r = hdr_at(a.rec, j, G, gg);
             uint64_t (&w)[HW] = hdr[qq];
             bool miss = false;
 #pragma unroll
@@ -395,10 +408,10 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(Gate gt, LuArgs a) {
               // never change once written, so the copies merge)
               uint64_t pa[HW], pb[HW];
 #pragma unroll
-              for (int i = 0; i < HW; ++i) pa[i] = load_agent(r + i);
+              for (int i = 0; i < HW; ++i) pa[i] = load_agent(r + i * hs);
               __builtin_amdgcn_s_sleep(8);
 #pragma unroll
-              for (int i = 0; i < HW; ++i) pb[i] = load_agent(r + i);
+              for (int i = 0; i < HW; ++i) pb[i] = load_agent(r + i * hs);
               long spins = 0;
               for (;;) {
                 miss = false;
@@ -409,7 +422,7 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(Gate gt, LuArgs a) {
                 }
                 if (!miss) break;
 #pragma unroll
-                for (int i = 0; i < HW; ++i) pa[i] = load_agent(r + i);
+                for (int i = 0; i < HW; ++i) pa[i] = load_agent(r + i * hs);
                 miss = false;
 #pragma unroll
                 for (int i = 0; i < HW; ++i) {
@@ -418,7 +431,7 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(Gate gt, LuArgs a) {
                 }
                 if (!miss) break;
 #pragma unroll
-                for (int i = 0; i < HW; ++i) pb[i] = load_agent(r + i);
+                for (int i = 0; i < HW; ++i) pb[i] = load_agent(r + i * hs);
                 if (++spins > kSpinLimit) {
                   to = true;
                   break;
@@ -473,7 +486,7 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(Gate gt, LuArgs a) {
                 break;
               }
               __builtin_amdgcn_s_sleep(1);
-              pay = load_agent(prev_rec + HW + lane);
+              pay = load_agent(prev_rec + lane);
             }
           }
           if (__any(to)) {
@@ -491,8 +504,8 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(Gate gt, LuArgs a) {
         if (lane >= jl + 1) sPs[lane - jl - 1] = pcur;
         wave_lds_sync();
         // this winner's payload: requested now, used at the next step
-        uint64_t* wrec = a.rec + ((long)j * G + wg) * RW;
-        pay = (lane < NB) ? load_agent(wrec + HW + lane) : 0;
+        uint64_t* wrec = pay_at(a.rec, j, G, wg);
+        pay = (lane < NB) ? load_agent(wrec + lane) : 0;
         prev_rec = wrec;
         if (lane == 0) {
           sRow[par][jl] = wrow;
@@ -549,7 +562,7 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(Gate gt, LuArgs a) {
               break;
             }
             __builtin_amdgcn_s_sleep(1);
-            pay = load_agent(prev_rec + HW + lane);
+            pay = load_agent(prev_rec + lane);
           }
         }
         if (__any(to)) {
@@ -680,7 +693,7 @@ size_t lu_records_bytes(int d, i64 ni, int max_steps) {
   const long G = (ni + 64L * rpt - 1) / (64L * rpt);
   long steps = std::min((long)d, (long)ni);
   if (max_steps > 0) steps = std::min(steps, (long)max_steps);
-  return (size_t)steps * G * RW * sizeof(uint64_t);
+  return (size_t)steps * step_words((int)G) * sizeof(uint64_t);
 }
 
 size_t lu_records_bytes_upto(int d, i64 n) {
