@@ -86,6 +86,12 @@ __device__ __forceinline__ void store_agent(uint64_t* p, uint64_t v) {
 __device__ __forceinline__ uint64_t load_agent(uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void store_agent_d(double* p, double v) {
+  store_agent(reinterpret_cast<uint64_t*>(p), dbits(v));
+}
+__device__ __forceinline__ double load_agent_d(const double* p) {
+  return bitsd(load_agent(reinterpret_cast<uint64_t*>(const_cast<double*>(p))));
+}
 __device__ __forceinline__ void store_agent_i32(int* p, int v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

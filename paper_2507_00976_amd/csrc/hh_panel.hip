@@ -19,6 +19,7 @@ constexpr int IB = 32;
 constexpr int NT = 256;
 constexpr int RWH = 2 * IB;
 constexpr uint64_t SENT = 0xFFF0DEADBEEFCAFEull;
+constexpr int kMaxLeafGroups = 256;  // workgroups of one leaf (rows / 256)
 
 struct LeafArgs {
   double* A;
@@ -93,16 +94,38 @@ __global__ __launch_bounds__(NT) void hh_leaf_kernel(Gate gt, LeafArgs a) {
         for (int c = 0; c < IB; ++c) store_agent(myrec + IB + c, dbits(x[c]));
       }
       // ---- combine all workgroups ----
+      // Every record word this thread sums is requested before the first
+      // wait (one memory round trip whatever G is); only words that had not
+      // landed yet are polled again.  The sum runs in workgroup order.
       {
         const int c = tid % IB, part = tid / IB;
+        const int owner = (int)(j / R);
+        uint64_t rowv = 0;
+        if (tid < IB && tid < ib && !to) rowv = load_agent(a.rec + ((long)j * G + owner) * RWH + IB + tid);
         double s = 0.0;
-        if (c >= j && c < ib)
-          for (int gg = part; gg < G; gg += 8) s += bitsd(poll_w(a.rec + ((long)j * G + gg) * RWH + c, to));
+        if (c >= j && c < ib) {
+          uint64_t v[kMaxLeafGroups / 8];
+#pragma unroll
+          for (int q = 0; q < kMaxLeafGroups / 8; ++q) {
+            const int gg = part + 8 * q;
+            v[q] = (gg < G && !to) ? load_agent(a.rec + ((long)j * G + gg) * RWH + c) : 0;
+          }
+#pragma unroll
+          for (int q = 0; q < kMaxLeafGroups / 8; ++q) {
+            const int gg = part + 8 * q;
+            if (gg < G) {
+              uint64_t w = v[q];
+              if (w == SENT) w = poll_w(a.rec + ((long)j * G + gg) * RWH + c, to);
+              s += bitsd(w);
+            }
+          }
+        }
         sAll[part][c] = s;
+        if (tid < IB && tid < ib) {
+          if (rowv == SENT) rowv = poll_w(a.rec + ((long)j * G + owner) * RWH + IB + tid, to);
+          sRow[tid] = bitsd(rowv);
+        }
       }
-      const int owner = (int)(j / R);
-      if (tid < IB && tid < ib)
-        sRow[tid] = bitsd(poll_w(a.rec + ((long)j * G + owner) * RWH + IB + tid, to));
       __syncthreads();
       if (tid < IB) {
         double s = 0.0;
@@ -164,7 +187,7 @@ int launch_hh_leaf(double* A, i64 lda, i64 mi, int ib, double* tau, uint64_t* re
   if (mi <= 0 || ib <= 0) return QRCP_OK;
   if (ib > IB) return QRCP_ERR_UNSUPPORTED;
   const int G = leaf_groups(mi);
-  if (G > 256) return QRCP_ERR_UNSUPPORTED;
+  if (G > kMaxLeafGroups) return QRCP_ERR_UNSUPPORTED;
   const size_t need = hh_leaf_records_bytes(mi);
   if (need > rec_bytes) return QRCP_ERR_WORKSPACE;
   QRCP_TRY(launch_fill_u64(rec, (i64)(need / 8), SENT, st));

@@ -18,6 +18,10 @@
 // double-buffered for this).  A workgroup publishes its last header of a panel
 // only after that background update is in memory, so a workgroup that has
 // read every header of the panel may read any pivot row's trailing values.
+// Rows that other workgroups read (the working copy and the background
+// update's results) are written with device-coherent stores and the pivot
+// rows are read with device-coherent loads, so no cache-wide writeback or
+// invalidation (an agent-scope fence) is needed anywhere in the loop.
 //
 // One pivot step costs one cross-workgroup round trip.  Every workgroup
 // publishes a record for its best candidate: a header (|x|, key = current
@@ -173,7 +177,7 @@ __device__ __forceinline__ void lu_tile_update(double* xw, long row0, int d, int
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int lr = (rb0 + g0 + rb) * 16 + 4 * r + k4;
-        if (act[lr] && col < d) xw[(row0 + lr) * d + col] = old[rb][r] - acc[r];
+        if (act[lr] && col < d) store_agent_d(xw + (row0 + lr) * d + col, old[rb][r] - acc[r]);
       }
     }
     if (RBG < NRBX) {
@@ -250,13 +254,13 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(Gate gt, LuArgs a) {
       const int c = (int)(e % d);
       const double v = a.msk[(row0 + r) * a.ld + c];
       bad |= !isfinite(v);
-      a.xw[(row0 + r) * d + c] = v;
+      store_agent_d(a.xw + (row0 + r) * d + c, v);
     }
     if (bad) sBad = 1;
   }
+  __builtin_amdgcn_s_waitcnt(0);  // the copy is in memory before any header goes out
   __syncthreads();
   const bool wg_bad = sBad != 0;
-  __threadfence();
 
   // row state (meaningful in wave 0)
   long row[RPT], pos[RPT];
@@ -588,7 +592,7 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(Gate gt, LuArgs a) {
 #pragma unroll
           for (int t0 = 0; t0 < NB; t0 += LUB) {
 #pragma unroll
-            for (int t = t0; t < t0 + LUB; ++t) u[t] = a.xw[sRow[pb][t] * (long)d + c0 + lane];
+            for (int t = t0; t < t0 + LUB; ++t) u[t] = load_agent_d(a.xw + sRow[pb][t] * (long)d + c0 + lane);
             __builtin_amdgcn_s_waitcnt(0);
             __builtin_amdgcn_sched_barrier(0);
           }
@@ -603,7 +607,7 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(Gate gt, LuArgs a) {
                               uc0 + cb * 16 + i16, sAct[pb], i16, k4);
         wave_lds_sync();
       }
-      __threadfence();  // release: the updated rows before wave 0's last header
+      __builtin_amdgcn_s_waitcnt(0);  // the updated rows are in memory before wave 0's last header
       if (lane == 0)
         __hip_atomic_fetch_add(&sTrailCnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
@@ -615,8 +619,6 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(Gate gt, LuArgs a) {
     // ---- this panel's update of the next panel's columns (all waves) ----
     // The rest of the trailing columns is updated by waves 1-3 during the
     // next panel's pivot steps.
-    // acquire: pivot rows' trailing values written by their owners
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     {
       constexpr int HRB = NRB / 2;
       const int cw = min(NB, d - pend);
@@ -634,7 +636,7 @@ __global__ __launch_bounds__(NT) void lu_pivots_kernel(Gate gt, LuArgs a) {
       if (tid < cw) {
         double u[NB];
 #pragma unroll
-        for (int t = 0; t < NB; ++t) u[t] = a.xw[sRow[par][t] * (long)d + pend + tid];
+        for (int t = 0; t < NB; ++t) u[t] = load_agent_d(a.xw + sRow[par][t] * (long)d + pend + tid);
         lu_forward_subst(u, sL11[par]);
 #pragma unroll
         for (int t = 0; t < NB; ++t) sU[t][tid] = u[t];
