@@ -61,14 +61,18 @@ __device__ __forceinline__ int mm_col(int r) {
   return 16 * (threadIdx.x >> 7) + 4 * r + ((threadIdx.x & 63) >> 4);
 }
 
-__device__ __forceinline__ void slot_load(double (*dst)[LDB], const double* src) {
-  for (int e = threadIdx.x; e < SLOT; e += NT) dst[e / BS][e % BS] = src[e];
+// Published blocks are written with device-coherent stores and read with
+// device-coherent loads, so a hand-off needs no cache-wide writeback or
+// invalidation (an agent-scope fence): the stores are complete before the
+// flag goes up, and the loads come after the flag was seen.
+__device__ __forceinline__ void slot_load(double (*dst)[LDB], double* src) {
+  for (int e = threadIdx.x; e < SLOT; e += NT) dst[e / BS][e % BS] = load_agent_d(src + e);
 }
 
-// Stores the LDS block to a slot and raises its flag to v (release).
+// Stores the LDS block to a slot and raises its flag to v.
 __device__ __forceinline__ void publish(double* slot, const double (*src)[LDB], int* flag, int v) {
-  for (int e = threadIdx.x; e < SLOT; e += NT) slot[e] = src[e / BS][e % BS];
-  __threadfence();
+  for (int e = threadIdx.x; e < SLOT; e += NT) store_agent_d(slot + e, src[e / BS][e % BS]);
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) store_agent_i32(flag, v);
 }
@@ -76,7 +80,7 @@ __device__ __forceinline__ void publish(double* slot, const double (*src)[LDB], 
 // Waits until both flags are nonzero (1 = published).  A flag value of 2, or
 // an abort word (may be null) naming a step at or before `step`, means the
 // value never comes.  Returns 1 (ready), 0 (abandoned) or -1 (timeout); uniform over the
-// workgroup, with an acquire fence when ready.
+// workgroup.
 __device__ int wait_flags(int* f1, int* f2, int* abort_word, int step, int* sres) {
   if (threadIdx.x == 0) {
     int res = 1;
@@ -93,9 +97,7 @@ __device__ int wait_flags(int* f1, int* f2, int* abort_word, int step, int* sres
     *sres = res;
   }
   __syncthreads();
-  const int res = *sres;
-  __threadfence();
-  return res;
+  return *sres;
 }
 
 __device__ __forceinline__ void atomic_min_agent(int* p, int v) {
@@ -298,8 +300,8 @@ __global__ __launch_bounds__(NT) void headlu_mw_kernel(Gate gt, double* Q, long 
     }
     __syncthreads();
     if (bi + 1 < nb) {
-      for (int e = tid; e < SLOT; e += NT) sl_linv(bi)[e] = sQ[e / BS][e % BS];
-      publish(sl(bi, bi), sP, fl(bi, bi), 1);  // its fence also covers L^{-1}
+      for (int e = tid; e < SLOT; e += NT) store_agent_d(sl_linv(bi) + e, sQ[e / BS][e % BS]);
+      publish(sl(bi, bi), sP, fl(bi, bi), 1);  // its store wait also covers L^{-1}
     }
   } else if (!stop) {
     const int p = pm;  // the diagonal block this panel block hangs off

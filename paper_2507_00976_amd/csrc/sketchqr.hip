@@ -7,7 +7,11 @@
 // been applied to them, publishes its reflectors V_p and their compact-WY
 // factor T_p, and raises flag p; workgroups w > p wait for the flag and apply
 // (I - V_p T_p V_p^T)^T to their own columns.  The panel factorization itself
-// is a column-by-column DLARFG + rank-1 update inside LDS.
+// is a column-by-column DLARFG + rank-1 update inside LDS.  V, T (and the
+// block columns of the full T) cross workgroups through device-coherent
+// stores and loads, and a flag goes up only after its data's stores have
+// completed, so no hand-off needs a cache-wide writeback or invalidation
+// (an agent-scope fence), which would also disturb whatever runs beside.
 //
 // Tail (the remaining ni - dh columns): R_tail = Q^T B_tail with the explicit
 // d x d Q = I - V T V^T, T from the UT transform of V^T V, all on the GEMM
@@ -54,7 +58,7 @@ __device__ void apply_panel_mfma(double* sC, int d, int ldc, const double* V, in
                                  double* sV, double* sW, double* sT, double* sW2) {
   constexpr int PW = 32;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int e = tid; e < PW * PW; e += NT) sT[e] = Tg[e];
+  for (int e = tid; e < PW * PW; e += NT) sT[e] = load_agent_d(Tg + e);
   hv4 acc = {0.0, 0.0, 0.0, 0.0};
   const int bi = w & 1, bj = w >> 1;
   for (int r0 = p0; r0 < d; r0 += VCH) {
@@ -62,7 +66,7 @@ __device__ void apply_panel_mfma(double* sC, int d, int ldc, const double* V, in
     __syncthreads();
     for (int e = tid; e < VCH * PW; e += NT) {
       const int rr = e % VCH, aa = e / VCH;
-      sV[aa * VLD + rr] = (rr < rows && aa < pc) ? V[(r0 + rr) + (long)(p0 + aa) * d] : 0.0;
+      sV[aa * VLD + rr] = (rr < rows && aa < pc) ? load_agent_d(V + (r0 + rr) + (long)(p0 + aa) * d) : 0.0;
     }
     __syncthreads();
     for (int k0 = 0; k0 < rows; k0 += 4) {
@@ -90,7 +94,7 @@ __device__ void apply_panel_mfma(double* sC, int d, int ldc, const double* V, in
     __syncthreads();
     for (int e = tid; e < VCH * PW; e += NT) {
       const int rr = e % VCH, aa = e / VCH;
-      sV[aa * VLD + rr] = (rr < rows && aa < pc) ? V[(r0 + rr) + (long)(p0 + aa) * d] : 0.0;
+      sV[aa * VLD + rr] = (rr < rows && aa < pc) ? load_agent_d(V + (r0 + rr) + (long)(p0 + aa) * d) : 0.0;
     }
     __syncthreads();
     const int nrb = (rows + 15) / 16;
@@ -159,18 +163,18 @@ __global__ __launch_bounds__(NT) void sketch_head_kernel(Gate gt, HeadArgs a) {
       if (tid == 0) store_agent_i32(a.status, QRCP_ERR_TIMEOUT);
       return;
     }
-    __threadfence();
+    // V_p and T_p are read with device-coherent loads: no fence needed
     if constexpr (PW == 32) {
       apply_panel_mfma(sC, d, ldc, a.V, p0, pc, a.T + (long)p * PW * PW, sV, sW, sT, sPart);
     } else {
-      for (int e = tid; e < PW * PW; e += NT) sT[e] = a.T[(long)p * PW * PW + e];
+      for (int e = tid; e < PW * PW; e += NT) sT[e] = load_agent_d(a.T + (long)p * PW * PW + e);
       for (int e = tid; e < PW * PW; e += NT) sW[e] = 0.0;
       __syncthreads();
       for (int r0 = p0; r0 < d; r0 += VCH) {
         const int rows = min(VCH, d - r0);
         for (int e = tid; e < VCH * PW; e += NT) {
           const int rr = e % VCH, aa = e / VCH;
-          sV[aa * VLD + rr] = (rr < rows && aa < pc) ? a.V[(r0 + rr) + (long)(p0 + aa) * d] : 0.0;
+          sV[aa * VLD + rr] = (rr < rows && aa < pc) ? load_agent_d(a.V + (r0 + rr) + (long)(p0 + aa) * d) : 0.0;
         }
         __syncthreads();
         for (int e = tid; e < PW * PW; e += NT) {
@@ -192,7 +196,7 @@ __global__ __launch_bounds__(NT) void sketch_head_kernel(Gate gt, HeadArgs a) {
         const int rows = min(VCH, d - r0);
         for (int e = tid; e < VCH * PW; e += NT) {
           const int rr = e % VCH, aa = e / VCH;
-          sV[aa * VLD + rr] = (rr < rows && aa < pc) ? a.V[(r0 + rr) + (long)(p0 + aa) * d] : 0.0;
+          sV[aa * VLD + rr] = (rr < rows && aa < pc) ? load_agent_d(a.V + (r0 + rr) + (long)(p0 + aa) * d) : 0.0;
         }
         __syncthreads();
         for (int e = tid; e < VCH * PW; e += NT) {
@@ -269,7 +273,7 @@ __global__ __launch_bounds__(NT) void sketch_head_kernel(Gate gt, HeadArgs a) {
       double v = sC[c * ldc + r];
       if (r > rc) v = (sInv[c] != 0.0) ? v / sInv[c] : 0.0;
       sC[c * ldc + r] = (r == rc) ? 1.0 : v;   // keep the scaled vector for T below
-      a.V[r + (long)rc * d] = (r < rc) ? 0.0 : (r == rc ? 1.0 : v);
+      store_agent_d(a.V + r + (long)rc * d, (r < rc) ? 0.0 : (r == rc ? 1.0 : v));
       if (r < rc) a.R[r + (long)rc * a.ldr] = v;
       else if (r > rc) a.R[r + (long)rc * a.ldr] = 0.0;
     }
@@ -307,8 +311,8 @@ __global__ __launch_bounds__(NT) void sketch_head_kernel(Gate gt, HeadArgs a) {
     }
   }
   __syncthreads();
-  for (int e = tid; e < PW * PW; e += NT) a.T[(long)w * PW * PW + e] = sT[e];
-  __threadfence();
+  for (int e = tid; e < PW * PW; e += NT) store_agent_d(a.T + (long)w * PW * PW + e, sT[e]);
+  __builtin_amdgcn_s_waitcnt(0);  // V and T (device-coherent stores) are in memory
   __syncthreads();
   if (tid == 0) store_agent_i32(a.flags + w, 1);
 }
@@ -383,7 +387,7 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(Gate gt, HeadArgs a
         if (tid == 0) store_agent_i32(a.status, QRCP_ERR_TIMEOUT);
         return false;
       }
-      __threadfence();
+      // V_p and T_p are read with device-coherent loads: no fence needed
       return true;
     };
     if (!wait_flag(1)) return;
@@ -395,7 +399,7 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(Gate gt, HeadArgs a
 #pragma unroll
       for (int q = 0; q < QV; ++q) {
         const int e = tid + NT * q, rr = e % DP, aa = e / DP;
-        vr[q] = (aa < pc && rr >= p0 && rr < d) ? a.V[rr + (long)(p0 + aa) * d] : 0.0;
+        vr[q] = (aa < pc && rr >= p0 && rr < d) ? load_agent_d(a.V + rr + (long)(p0 + aa) * d) : 0.0;
       }
 #pragma unroll
       for (int q = 0; q < QV; ++q) {
@@ -440,7 +444,7 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(Gate gt, HeadArgs a
       constexpr int QT = PWR * PWR / NT;
       double tr[QT];
 #pragma unroll
-      for (int q = 0; q < QT; ++q) tr[q] = a.T[(long)p * PWR * PWR + tid + NT * q];
+      for (int q = 0; q < QT; ++q) tr[q] = load_agent_d(a.T + (long)p * PWR * PWR + tid + NT * q);
 #pragma unroll
       for (int q = 0; q < QT; ++q) {
         const int e = tid + NT * q;
@@ -498,7 +502,7 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(Gate gt, HeadArgs a
       if (cl < ncol) {
         const int rc = c0 + cl;
         const double v = h ? v1 : v0;
-        a.V[r + (long)rc * d] = (r < rc) ? 0.0 : (r == rc ? 1.0 : v / sInv[cl]);
+        store_agent_d(a.V + r + (long)rc * d, (r < rc) ? 0.0 : (r == rc ? 1.0 : v / sInv[cl]));
         a.R[r + (long)rc * a.ldr] = (r <= rc) ? v : 0.0;
       }
     }
@@ -613,7 +617,7 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(Gate gt, HeadArgs a
   // workgroups start forming V^T C while T is computed ----
 #pragma unroll
   for (int i = 0; i < NR2; ++i) emit(i, x0[i], x1[i]);
-  __threadfence();
+  __builtin_amdgcn_s_waitcnt(0);  // V (device-coherent stores) is in memory
   __syncthreads();
   if (tid == 0) store_agent_i32(a.flags + w, 1);
 
@@ -648,9 +652,9 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(Gate gt, HeadArgs a
 
   for (int e = tid; e < PWR * PWR; e += NT) {
     const int i = e % PWR, jj = e / PWR;
-    a.T[(long)w * PWR * PWR + e] = (i < ncol && jj < ncol) ? sT[i * LDP + jj] : 0.0;
+    store_agent_d(a.T + (long)w * PWR * PWR + e, (i < ncol && jj < ncol) ? sT[i * LDP + jj] : 0.0);
   }
-  __threadfence();
+  __builtin_amdgcn_s_waitcnt(0);  // T (device-coherent stores) is in memory
   __syncthreads();
   if (tid == 0) store_agent_i32(a.flags + w, 2);
 
@@ -665,30 +669,30 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(Gate gt, HeadArgs a
     const int li = lane & 15, lk = lane >> 4;
     for (int e = tid; e < PWR * PWR; e += NT) {
       const int i = e % PWR, jj = e / PWR;
-      if (i < ncol && jj < ncol) a.Tfull[(c0 + i) + (long)(c0 + jj) * ldt] = sT[i * LDP + jj];
+      if (i < ncol && jj < ncol) store_agent_d(a.Tfull + (c0 + i) + (long)(c0 + jj) * ldt, sT[i * LDP + jj]);
     }
     // T is upper triangular: zero below the diagonal block
     const int below = dh - c0 - ncol;
     for (int e = tid; e < below * ncol; e += NT)
-      a.Tfull[(c0 + ncol + e % below) + (long)(c0 + e / below) * ldt] = 0.0;
+      store_agent_d(a.Tfull + (c0 + ncol + e % below) + (long)(c0 + e / below) * ldt, 0.0);
     if (w > 0) {
       // V_w, rows c0 .. d-1 (zero above), to LDS as [k][j], k = row - c0
       const int K = d - c0;
       for (int e = tid; e < K * PWR; e += NT) {
         const int k = e % K, jj = e / K;
-        sV[k * LDP + jj] = (jj < ncol) ? a.V[(c0 + k) + (long)(c0 + jj) * d] : 0.0;
+        sV[k * LDP + jj] = (jj < ncol) ? load_agent_d(a.V + (c0 + k) + (long)(c0 + jj) * d) : 0.0;
       }
       __syncthreads();
       for (int I = 0; I < w; ++I) {
         // Y_I = V_I^T V_w over rows c0 .. d-1: A(i, k) = V(c0 + k, 32 I + i)
-        const double* vcol = a.V + (long)(PWR * I + 16 * qi + li) * d + c0;
+        const double* vcol = a.V + (long)(PWR * I + 16 * qi + li) * d + c0;  // device-coherent loads
         dv4 acc = dv4{0.0, 0.0, 0.0, 0.0};
         for (int k0 = 0; k0 < K; k0 += 32) {
           double av[8];
 #pragma unroll
           for (int b = 0; b < 8; ++b) {
             const int k = k0 + 4 * b + lk;
-            av[b] = (k < K) ? vcol[k] : 0.0;
+            av[b] = (k < K) ? load_agent_d(vcol + k) : 0.0;
           }
 #pragma unroll
           for (int b = 0; b < 8; ++b) {
@@ -712,7 +716,7 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(Gate gt, HeadArgs a
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int jj = 16 * qj + 4 * r + lk;
-          if (jj < ncol) a.Tfull[(PWR * I + 16 * qi + li) + (long)(c0 + jj) * ldt] = acc2[r];
+          if (jj < ncol) store_agent_d(a.Tfull + (PWR * I + 16 * qi + li) + (long)(c0 + jj) * ldt, acc2[r]);
         }
         __syncthreads();
       }
@@ -731,7 +735,7 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(Gate gt, HeadArgs a
         if (tid == 0) store_agent_i32(a.status, QRCP_ERR_TIMEOUT);
         return;
       }
-      __threadfence();
+      // earlier block columns are read with device-coherent loads: no fence needed
       // Z_I = -sum_{J=I}^{w-1} T(I, J) Y'_J for I = 0 .. w-1, written over Y'_I
       for (int I = 0; I < w; ++I) {
         dv4 acc = dv4{0.0, 0.0, 0.0, 0.0};
@@ -740,9 +744,9 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(Gate gt, HeadArgs a
 #pragma unroll
           for (int s = 0; s < 8; ++s) {
             const int k = 4 * s + lk;
-            av[s] = a.Tfull[(PWR * I + 16 * qi + li) + (long)(PWR * J + k) * ldt];
+            av[s] = load_agent_d(a.Tfull + (PWR * I + 16 * qi + li) + (long)(PWR * J + k) * ldt);
             const int jj = 16 * qj + li;
-            bv[s] = (jj < ncol) ? a.Tfull[(PWR * J + k) + (long)(c0 + jj) * ldt] : 0.0;
+            bv[s] = (jj < ncol) ? load_agent_d(a.Tfull + (PWR * J + k) + (long)(c0 + jj) * ldt) : 0.0;
           }
 #pragma unroll
           for (int s = 0; s < 8; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[s], av[s], acc, 0, 0, 0);
@@ -751,12 +755,12 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(Gate gt, HeadArgs a
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int jj = 16 * qj + 4 * r + lk;
-          if (jj < ncol) a.Tfull[(PWR * I + 16 * qi + li) + (long)(c0 + jj) * ldt] = -acc[r];
+          if (jj < ncol) store_agent_d(a.Tfull + (PWR * I + 16 * qi + li) + (long)(c0 + jj) * ldt, -acc[r]);
         }
         __syncthreads();
       }
     }
-    __threadfence();
+    __builtin_amdgcn_s_waitcnt(0);  // this block column is in memory
     __syncthreads();
     if (tid == 0) store_agent_i32(a.tflags + w, 1);
   }
