@@ -64,13 +64,19 @@ __global__ __launch_bounds__(NT) void hh_leaf_kernel(Gate gt, LeafArgs a) {
   if (tid == 0) sflag = 0;
   __syncthreads();
 
+  // The column loop is not unrolled (its body is long); the row's values stay
+  // in registers because every access below names its column at compile time
+  // (the pivot column is picked by a select over the unrolled columns), so
+  // nothing is indexed by the loop counter.
+  for (int j = 0; j < ib; ++j) {
+    {
+      double xj = 0.0;
 #pragma unroll
-  for (int j = 0; j < IB; ++j) {
-    if (j < ib) {
+      for (int c = 0; c < IB; ++c) xj = (c == j) ? x[c] : xj;
       // ---- partial sums of my row: slot j = x_j^2, slot c > j = x_j x_c ----
       const bool below = mine && r > j;
 #pragma unroll
-      for (int c = 0; c < IB; ++c) sRed[wv][lane][c] = (below && c >= j) ? x[j] * x[c] : 0.0;
+      for (int c = 0; c < IB; ++c) sRed[wv][lane][c] = (below && c >= j) ? xj * x[c] : 0.0;
       __syncthreads();
       {
         // 256 threads: column c = tid % 32, part = tid / 32 (8 parts x 32 rows)
@@ -148,7 +154,7 @@ __global__ __launch_bounds__(NT) void hh_leaf_kernel(Gate gt, LeafArgs a) {
       }
       if (g == 0 && tid == 0) a.tau[j] = tau;
       if (mine && r >= j) {
-        const double v = (r == j) ? 1.0 : (xx != 0.0 ? x[j] / inv : 0.0);
+        const double v = (r == j) ? 1.0 : (xx != 0.0 ? xj / inv : 0.0);
         if (tau != 0.0) {
 #pragma unroll
           for (int c = 0; c < IB; ++c) {
@@ -158,7 +164,9 @@ __global__ __launch_bounds__(NT) void hh_leaf_kernel(Gate gt, LeafArgs a) {
             }
           }
         }
-        x[j] = (r == j) ? beta : v;
+        const double xn = (r == j) ? beta : v;
+#pragma unroll
+        for (int c = 0; c < IB; ++c) x[c] = (c == j) ? xn : x[c];
       }
       __syncthreads();
     }
