@@ -50,6 +50,7 @@ __global__ __launch_bounds__(NT) void hh_leaf_kernel(Gate gt, LeafArgs a) {
   __shared__ double sAll[8][IB];
   __shared__ double sTot[IB];
   __shared__ double sRow[IB];
+  __shared__ double sF[IB];  // tau (v^T a_c) of the column's reflector, per later column c
   __shared__ int sflag;
   const int g = blockIdx.x, G = gridDim.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -153,16 +154,15 @@ __global__ __launch_bounds__(NT) void hh_leaf_kernel(Gate gt, LeafArgs a) {
         inv = alpha - beta;
       }
       if (g == 0 && tid == 0) a.tau[j] = tau;
+      // the reflector's action on each later column, formed once per column
+      if (tid < IB) sF[tid] = (tid > j && tid < ib) ? tau * (sRow[tid] + sTot[tid] / inv) : 0.0;
+      __syncthreads();
       if (mine && r >= j) {
         const double v = (r == j) ? 1.0 : (xx != 0.0 ? xj / inv : 0.0);
         if (tau != 0.0) {
 #pragma unroll
-          for (int c = 0; c < IB; ++c) {
-            if (c > j && c < ib) {
-              const double w = sRow[c] + sTot[c] / inv;
-              x[c] -= tau * w * v;
-            }
-          }
+          for (int c = 0; c < IB; ++c)
+            if (c > j && c < ib) x[c] -= sF[c] * v;
         }
         const double xn = (r == j) ? beta : v;
 #pragma unroll
