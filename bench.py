@@ -117,7 +117,8 @@ def pmc_table(paths, n):
     run's largest device-to-device copy, the restore of the n x n input: 8 n^2
     bytes read and written) and GB/s; SQ_INSTS_VALU_MFMA_MOPS_* as TFLOP/s
     (512 flops per MOP) and SQ_VALU_MFMA_BUSY_CYCLES over GRBM_GUI_ACTIVE
-    (summed over the 8 XCDs) as the busy share of the 1024 SIMDs' MFMA units."""
+    (summed over the 8 XCDs) as the busy share of the 1024 SIMDs' MFMA units.
+    Only the library's kernels that take at least 0.3 % of its kernel time."""
     import csv
     import re
     per = {}     # (dispatch) -> {"name", "dur", counter: value}
@@ -141,13 +142,14 @@ def pmc_table(paths, n):
             scale[c] = copy_kib / max(cp)
 
     def short(name):
+        name = name.replace("(anonymous namespace)::", "")
         name = re.sub(r"\(.*$", "", name)
         name = re.sub(r"^void ", "", name).replace("qrcp::", "")
         return name
 
     groups = {}
     for r in per.values():
-        if "copyBuffer" in r["name"] or not r["name"]:
+        if "copyBuffer" in r["name"] or "qrcp::" not in r["name"]:
             continue
         g = groups.setdefault(short(r["name"]), [])
         g.append(r)
@@ -187,7 +189,9 @@ def pmc_table(paths, n):
             cells.append(f"{100.0 * busy / (act * 1024.0):.1f}" if act > 0 else "")
         rows.append((dur, "| " + " | ".join(cells) + " |"))
     rows.sort(key=lambda t: -t[0])
-    lines += [r for _, r in rows if _ > 0]
+    total = sum(t for t, _ in rows)
+    # the library's kernels that take at least 0.3 % of its kernel time
+    lines += [r for t, r in rows if t >= 0.003 * total]
     print("\n".join(lines))
 
 
