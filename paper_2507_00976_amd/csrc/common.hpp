@@ -86,6 +86,31 @@ __device__ __forceinline__ void store_agent(uint64_t* p, uint64_t v) {
 __device__ __forceinline__ uint64_t load_agent(uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// v(lane) + v(lane ^ 16) and v(lane) + v(lane ^ 32) for a double, with the
+// gfx950 row-swap moves (v_permlane16_swap / v_permlane32_swap, one VALU
+// instruction per 32-bit half) instead of an LDS-routed shuffle.  With both
+// operands equal, the swap returns the even-row (lower-half) copy in the
+// first result and the odd-row (upper-half) copy in the second, in every
+// lane; their sum is the same in both partner lanes.
+__device__ __forceinline__ double xsum_lanes16(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+  const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  const double e = __longlong_as_double((long long)(((unsigned long long)h[0] << 32) | l[0]));
+  const double o = __longlong_as_double((long long)(((unsigned long long)h[1] << 32) | l[1]));
+  return e + o;
+}
+__device__ __forceinline__ double xsum_lanes32(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+  const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  const double e = __longlong_as_double((long long)(((unsigned long long)h[0] << 32) | l[0]));
+  const double o = __longlong_as_double((long long)(((unsigned long long)h[1] << 32) | l[1]));
+  return e + o;
+}
+
 __device__ __forceinline__ void store_agent_d(double* p, double v) {
   store_agent(reinterpret_cast<uint64_t*>(p), dbits(v));
 }

@@ -190,7 +190,8 @@ __device__ __forceinline__ void lu_tile_update(double* xw, long row0, int d, int
 // u := L11^{-1} u for the unit lower triangular L11 of a panel (rows 16-byte
 // aligned in LDS, read two multipliers at a time by every lane at once).  Row
 // t + 1 is requested before row t is applied, so each LDS round trip overlaps
-// a row of arithmetic instead of a single multiply-add.
+// a row of arithmetic; each row's sum runs in four interleaved partial sums,
+// so its dependency chain is a quarter of the row long.
 __device__ __forceinline__ void lu_forward_subst(double (&u)[NB], const double (*L)[NB + 2]) {
   double2 cur[NB / 2], nxt[NB / 2];
   nxt[0] = reinterpret_cast<const double2*>(L[1])[0];
@@ -203,13 +204,13 @@ __device__ __forceinline__ void lu_forward_subst(double (&u)[NB], const double (
       for (int s2 = 0; 2 * s2 < t + 1; ++s2)
         nxt[s2] = reinterpret_cast<const double2*>(L[t + 1])[s2];
     }
-    double acc = u[t];
+    double acc[4] = {u[t], 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int s2 = 0; 2 * s2 < t; ++s2) {
-      acc -= cur[s2].x * u[2 * s2];
-      if (2 * s2 + 1 < t) acc -= cur[s2].y * u[2 * s2 + 1];
+    for (int s = 0; s < t; ++s) {
+      const double l = (s & 1) ? cur[s >> 1].y : cur[s >> 1].x;
+      acc[s & 3] -= l * u[s];
     }
-    u[t] = acc;
+    u[t] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   }
 }
 

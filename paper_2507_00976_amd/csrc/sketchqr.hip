@@ -350,7 +350,7 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(Gate gt, HeadArgs a
   double* sRed = sXb + DP;                 // 2 x 4 x PWR: per-wave column sums
   double* sRowJ = sRed + 2 * 4 * PWR;      // 2 x PWR: row rj of the panel
   double* sTau = sRowJ + 2 * PWR;          // PWR
-  double* sInv = sTau + PWR;               // PWR: alpha_j - beta_j (1 when tau_j = 0)
+  double* sInv = sTau + PWR;               // PWR: 1 / (alpha_j - beta_j) (1 when tau_j = 0)
   __shared__ int sbad;
 
   const int w = blockIdx.x;
@@ -502,7 +502,7 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(Gate gt, HeadArgs a
       if (cl < ncol) {
         const int rc = c0 + cl;
         const double v = h ? v1 : v0;
-        store_agent_d(a.V + r + (long)rc * d, (r < rc) ? 0.0 : (r == rc ? 1.0 : v / sInv[cl]));
+        store_agent_d(a.V + r + (long)rc * d, (r < rc) ? 0.0 : (r == rc ? 1.0 : v * sInv[cl]));
         a.R[r + (long)rc * a.ldr] = (r <= rc) ? v : 0.0;
       }
     }
@@ -549,10 +549,10 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(Gate gt, HeadArgs a
       }
     }
     double s0 = s0a + s0b, s1 = s1a + s1b;
-    s0 += __shfl_xor(s0, 16, 64);
-    s1 += __shfl_xor(s1, 16, 64);
-    s0 += __shfl_xor(s0, 32, 64);
-    s1 += __shfl_xor(s1, 32, 64);
+    s0 = xsum_lanes16(s0);
+    s1 = xsum_lanes16(s1);
+    s0 = xsum_lanes32(s0);
+    s1 = xsum_lanes32(s1);
     wave_lds_sync();  // this step's reads of sXb before the next step's writes
     if (kk == 0) {
       sRed[(buf * 4 + ws) * PWR + j] = s0;
@@ -568,19 +568,21 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(Gate gt, HeadArgs a
     const double S1 = (red[16 + j] + red[PWR + 16 + j]) + (red[2 * PWR + 16 + j] + red[3 * PWR + 16 + j]);
     const double xx = (red[jc] + red[PWR + jc]) + (red[2 * PWR + jc] + red[3 * PWR + jc]);
     const double alpha = sRowJ[buf * PWR + jc];
-    double beta = alpha, tau = 0.0, inv = 1.0;
+    // DLARFG: v = x / (alpha - beta) is formed, as LAPACK does, with the
+    // reciprocal rinv = 1 / (alpha - beta)
+    double beta = alpha, tau = 0.0, rinv = 1.0;
     if (xx != 0.0) {
       const double nrm = sqrt(alpha * alpha + xx);
       beta = (alpha < 0.0) ? nrm : -nrm;
       tau = (beta - alpha) / beta;
-      inv = alpha - beta;
+      rinv = 1.0 / (alpha - beta);
     }
     if (tau != 0.0) {
       // the reflector acts on my columns to the right of jc
       const bool u0c = j > jc && j < ncol, u1c = 16 + j > jc && 16 + j < ncol;
-      const double f0 = u0c ? tau * (sRowJ[buf * PWR + j] + S0 / inv) : 0.0;
-      const double f1 = u1c ? tau * (sRowJ[buf * PWR + 16 + j] + S1 / inv) : 0.0;
-      const double fv0 = f0 / inv, fv1 = f1 / inv;
+      const double f0 = u0c ? tau * (sRowJ[buf * PWR + j] + S0 * rinv) : 0.0;
+      const double f1 = u1c ? tau * (sRowJ[buf * PWR + 16 + j] + S1 * rinv) : 0.0;
+      const double fv0 = f0 * rinv, fv1 = f1 * rinv;
       x0[0] -= fv0 * xj[0] + (holder ? f0 : 0.0);
       x1[0] -= fv1 * xj[0] + (holder ? f1 : 0.0);
 #pragma unroll
@@ -590,16 +592,16 @@ __global__ __launch_bounds__(NT) void sketch_head_reg_kernel(Gate gt, HeadArgs a
       }
     }
     if (holder && j == jl) xc[0] = beta;
-    // G(i, jc) = v_i^T v_jc = (x_i(rj) + S_i / inv_jc) / inv_i for i < jc
+    // G(i, jc) = v_i^T v_jc = (x_i(rj) + S_i rinv_jc) rinv_i for i < jc
     if (tid < PWR) {
       const int i = tid;
       if (i < jc) {
         const double Si = (red[i] + red[PWR + i]) + (red[2 * PWR + i] + red[3 * PWR + i]);
-        sG[i * LDP + jc] = (sRowJ[buf * PWR + i] + Si / inv) / sInv[i];
+        sG[i * LDP + jc] = (sRowJ[buf * PWR + i] + Si * rinv) * sInv[i];
       }
       if (i == 0) {
         sTau[jc] = tau;
-        sInv[jc] = inv;
+        sInv[jc] = rinv;
         a.tau[rj] = tau;
       }
     }
