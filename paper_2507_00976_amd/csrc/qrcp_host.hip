@@ -146,6 +146,8 @@ struct FactorWs {
   double *G, *Rc, *Rinv, *Tm, *P, *X, *Uinv, *R11inv, *R2, *RcN;
   double* dsig;
   double *W, *W2;
+  double* Z;       // b x n: Q2^T C2 of the Cholesky-QR panel (formed beside the reconstruction)
+  double* split2;  // split-K partials of that product (2 b n doubles)
   double *colss, *ref;
   int *status, *kdev, *info;
   double* split;
@@ -184,6 +186,8 @@ size_t carve_factor(char* base, i64 m, i64 n, i64 b, int d, FactorWs* w, bool hq
   w->dsig = c.take<double>(bb);
   w->W = c.take<double>((size_t)bb * n);
   w->W2 = c.take<double>((size_t)bb * n);
+  w->Z = c.take<double>((size_t)bb * n);
+  w->split2 = c.take<double>((size_t)2 * bb * n);
   w->colss = c.take<double>(n + 1);
   w->ref = c.take<double>(1);
   w->status = c.take<int>(4);
@@ -568,6 +572,11 @@ int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
     if (!lu_all_steps) lu_steps = kmax;
     else if (mi < std::min<i64>(d, ni)) lu_steps = (int)mi;
     double* Ablk = A + s + s * lda;  // panel top-left (rows s.., physical column s)
+    const i64 nc = n - c;
+    double* Ct = A + s + c * lda;  // trailing columns c .. n-1, rows s..m-1
+    // W of the trailing update split as Y1^T C1 + U^{-T} (Q2^T C2) (Cholesky-QR
+    // panel, FP64 update, rows below the panel and columns right of it)
+    const bool zsplit = o.qr_tall == 0 && tprec == Prec::F64 && mi > kmax && nc > 0;
     // 1. pivots of the sketch (Alg. 2 GETRF on the transpose, or GEQP3)
     if (o.qrcp_wide == 1) {
       // column-pivoted QR of the sketch (GEQP3): pivots and R^sk in one pass,
@@ -707,6 +716,29 @@ int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
                         nullptr, 0, st));
         }
       }
+      // W = Y^T C of the trailing update, with Y = [Y1; Q2 U^{-1}] from the
+      // reconstruction below, is Y1^T C1 + U^{-T} (Q2^T C2): the large product
+      // Z = Q2^T C2 needs only the Cholesky-QR panel, so it runs on the second
+      // stream beside the reconstruction and T (on the caller's stream in
+      // order when there is no second stream: the same arithmetic)
+      if (zsplit) {
+        hipStream_t zs = st;
+        if (lookahead) {
+          QRCP_HIP(hipEventRecord(aux->fork, st));
+          QRCP_HIP(hipStreamWaitEvent(aux->s, aux->fork, 0));
+          zs = aux->s;
+        }
+        {
+          ProfScope psz(kStTrailW, 2.0 * (mi - kmax) * kmax * nc, zs);
+          GemmArgs z = ga(kmax, (int)nc, (int)(mi - kmax), Ablk + kmax, lda, Ct + kmax, lda, w.Z, kmax);
+          z.kind = GemmKind::TrailingW;
+          QRCP_TRY(gemm(true, false, Prec::F64, z, w.split2, (size_t)2 * b * n * sizeof(double), zs));
+        }
+        if (lookahead) {
+          QRCP_HIP(hipEventRecord(aux->join, zs));
+          jg.pending = true;
+        }
+      }
       // 9. Householder reconstruction: sign-modified LU of the head, Y2 = Q2 U^{-1}
       {
         ProfScope psr(kStRecon, 2.0 * (mi - kmax) * kmax * kmax + 2.0 * kmax * kmax * kmax, st);
@@ -721,7 +753,8 @@ int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
           QRCP_TRY(gemm(false, false, Prec::F64,
                         ga((int)(mi - kmax), kmax, kmax, Ablk + kmax, lda, w.Uinv, b, w.Y + kmax, m),
                         nullptr, 0, st));
-          QRCP_TRY(launch_copy2d(w.Y + kmax, m, Ablk + kmax, lda, mi - kmax, kmax, st));
+          // Y2 into the output below the head (after Z, which still reads Q2 there)
+          if (!zsplit) QRCP_TRY(launch_copy2d(w.Y + kmax, m, Ablk + kmax, lda, mi - kmax, kmax, st));
         }
         QRCP_TRY(launch_unit_lower(Ablk, lda, kmax, w.Y, m, st));
         //    R11 = diag(D) Rc Rsk(0:k, 0:k)
@@ -730,10 +763,23 @@ int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
       }
     }
     // 10-11. trailing update of the physical columns c .. n-1 (rows s..m-1)
-    const i64 nc = n - c;
-    double* Ct = A + s + c * lda;
-    QRCP_TRY(apply_qt_w(w.Y, mi, kmax, m, tau + s, Ct, nc, lda, tprec, w.Tm, w.R11inv, b, w.W, w.W2,
-                        w.split, kSplitBytes, st));
+    if (zsplit) {
+      QRCP_TRY(apply_qt_t(w.Y, mi, kmax, m, tau + s, w.Tm, w.R11inv, b, w.split, kSplitBytes, st));
+      QRCP_TRY(jg.join());
+      QRCP_TRY(launch_copy2d(w.Y + kmax, m, Ablk + kmax, lda, mi - kmax, kmax, st));
+      ProfScope psw(kStTrailW, 4.0 * kmax * kmax * nc, st);
+      // W = U^{-T} Z + Y1^T C1, W2 = -T^T W
+      QRCP_TRY(gemm(true, false, Prec::F64, ga(kmax, (int)nc, kmax, w.Uinv, b, w.Z, kmax, w.W, kmax),
+                    nullptr, 0, st));
+      QRCP_TRY(gemm(true, false, Prec::F64,
+                    ga(kmax, (int)nc, kmax, w.Y, m, Ct, lda, w.W, kmax, 1.0, 1.0), nullptr, 0, st));
+      QRCP_TRY(gemm(true, false, Prec::F64,
+                    ga(kmax, (int)nc, kmax, w.R11inv, b, w.W, kmax, w.W2, kmax, -1.0, 0.0), nullptr, 0,
+                    st));
+    } else {
+      QRCP_TRY(apply_qt_w(w.Y, mi, kmax, m, tau + s, Ct, nc, lda, tprec, w.Tm, w.R11inv, b, w.W,
+                          w.W2, w.split, kSplitBytes, st));
+    }
     {
       // a block that stops before its width: the k reflectors applied to the
       // saved panel columns k .. k_max, which become R(0:k, k:k_max) and the
