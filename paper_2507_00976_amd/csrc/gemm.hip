@@ -567,16 +567,19 @@ static int tile_override() {
 // waves (each a 64 x 32 block) -- measured at 16384^2, b = 256: rank-k update
 // 55 vs 47 TFLOP/s, W = Y^T C 56 vs 52 TFLOP/s -- unless their 128 x 128
 // tiles fill less than one wave of the device's resident slots (two per
-// compute unit) and K is too short to split (or the product is the sketch,
-// d = 320 rows, whose third 128-row tile row would be a sixth empty): those
-// take the 64 x 64 tiles with 16-byte loads.  Both compute the same
+// compute unit) and K is too short to split, or the output is at most 64
+// wide (or the product is the sketch, d = 320 rows, whose third 128-row tile
+// row would be a sixth empty): those take the 64 x 64 tiles with 16-byte
+// loads.  Both compute the same
 // per-element sums, so the results do not depend on the choice.
 static int pick_cfg(const GemmArgs& g, bool f64) {
   int cfg = tile_override();
   if (f64 && cfg == 0 && vec_ok(g)) {
     const long tiles = (long)((g.M + 127) / 128) * ((g.N + 127) / 128);
     const bool small = tiles < 2L * 256 && g.K < 512;
-    cfg = (g.kind == GemmKind::Sketch || small) ? 9 : 12;
+    // an output at most 64 wide would leave most of a 128-wide tile empty
+    const bool skinny = g.M <= 64 || g.N <= 64;
+    cfg = (g.kind == GemmKind::Sketch || small || skinny) ? 9 : 12;
   }
   return cfg;
 }

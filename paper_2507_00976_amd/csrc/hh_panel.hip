@@ -29,6 +29,8 @@ struct LeafArgs {
   double* tau;
   uint64_t* rec;
   int* status;
+  double* gram;  // may be null: strict upper triangle of V^T V (ib x ib, ld ldg)
+  long ldg;
 };
 
 __device__ __forceinline__ uint64_t poll_w(uint64_t* p, bool& to) {
@@ -74,10 +76,11 @@ __global__ __launch_bounds__(NT) void hh_leaf_kernel(Gate gt, LeafArgs a) {
       double xj = 0.0;
 #pragma unroll
       for (int c = 0; c < IB; ++c) xj = (c == j) ? x[c] : xj;
-      // ---- partial sums of my row: slot j = x_j^2, slot c > j = x_j x_c ----
+      // ---- partial sums of my row: slot j = x_j^2, slot c > j = x_j x_c, and
+      // slot c < j = x_j v_c (v_c, the earlier reflectors, for the Gram) ----
       const bool below = mine && r > j;
 #pragma unroll
-      for (int c = 0; c < IB; ++c) sRed[wv][lane][c] = (below && c >= j) ? xj * x[c] : 0.0;
+      for (int c = 0; c < IB; ++c) sRed[wv][lane][c] = below ? xj * x[c] : 0.0;
       __syncthreads();
       {
         // 256 threads: column c = tid % 32, part = tid / 32 (8 parts x 32 rows)
@@ -110,7 +113,7 @@ __global__ __launch_bounds__(NT) void hh_leaf_kernel(Gate gt, LeafArgs a) {
         uint64_t rowv = 0;
         if (tid < IB && tid < ib && !to) rowv = load_agent(a.rec + ((long)j * G + owner) * RWH + IB + tid);
         double s = 0.0;
-        if (c >= j && c < ib) {
+        if (c < ib) {
           uint64_t v[kMaxLeafGroups / 8];
 #pragma unroll
           for (int q = 0; q < kMaxLeafGroups / 8; ++q) {
@@ -154,6 +157,9 @@ __global__ __launch_bounds__(NT) void hh_leaf_kernel(Gate gt, LeafArgs a) {
         inv = alpha - beta;
       }
       if (g == 0 && tid == 0) a.tau[j] = tau;
+      // V^T V of the leaf: v_c^T v_j = v_c(j) + (sum over rows below j of
+      // v_c x_j) / (alpha - beta), for c < j (v_c(j) is the owner's row)
+      if (a.gram && g == 0 && tid < j) a.gram[tid + j * a.ldg] = sRow[tid] + sTot[tid] / inv;
       // the reflector's action on each later column, formed once per column
       if (tid < IB) sF[tid] = (tid > j && tid < ib) ? tau * (sRow[tid] + sTot[tid] / inv) : 0.0;
       __syncthreads();
@@ -191,7 +197,7 @@ size_t hh_leaf_records_bytes(i64 mi) {
 }
 
 int launch_hh_leaf(double* A, i64 lda, i64 mi, int ib, double* tau, uint64_t* rec,
-                   size_t rec_bytes, int* status, hipStream_t st) {
+                   size_t rec_bytes, int* status, hipStream_t st, double* gram, i64 ldg) {
   if (mi <= 0 || ib <= 0) return QRCP_OK;
   if (ib > IB) return QRCP_ERR_UNSUPPORTED;
   const int G = leaf_groups(mi);
@@ -199,7 +205,7 @@ int launch_hh_leaf(double* A, i64 lda, i64 mi, int ib, double* tau, uint64_t* re
   const size_t need = hh_leaf_records_bytes(mi);
   if (need > rec_bytes) return QRCP_ERR_WORKSPACE;
   QRCP_TRY(launch_fill_u64(rec, (i64)(need / 8), SENT, st));
-  LeafArgs args{A, (long)lda, (long)mi, ib, tau, rec, status};
+  LeafArgs args{A, (long)lda, (long)mi, ib, tau, rec, status, gram, (long)ldg};
   Gate gt = current_gate();
   void* params[] = {&gt, &args};
   QRCP_TRY(launch_resident((const void*)hh_leaf_kernel, dim3(G), dim3(NT), params, 0, st));
