@@ -11,6 +11,7 @@
 // the exchanged sums: v^T a_c = a_c(j) + (x^T a_c)/(alpha - beta).
 #include "common.hpp"
 #include "kernels.hpp"
+#include "wave32.hpp"
 
 namespace qrcp {
 
@@ -29,8 +30,8 @@ struct LeafArgs {
   double* tau;
   uint64_t* rec;
   int* status;
-  double* gram;  // may be null: strict upper triangle of V^T V (ib x ib, ld ldg)
-  long ldg;
+  double* tout;  // may be null: T of the leaf's compact WY form (ib x ib, ld ldt)
+  long ldt;
 };
 
 __device__ __forceinline__ uint64_t poll_w(uint64_t* p, bool& to) {
@@ -53,6 +54,8 @@ __global__ __launch_bounds__(NT) void hh_leaf_kernel(Gate gt, LeafArgs a) {
   __shared__ double sTot[IB];
   __shared__ double sRow[IB];
   __shared__ double sF[IB];  // tau (v^T a_c) of the column's reflector, per later column c
+  __shared__ double sGm[IB][IB + 1];  // V^T V (strict upper triangle), then the UT matrix
+  __shared__ double sTauL[IB];
   __shared__ int sflag;
   const int g = blockIdx.x, G = gridDim.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -159,7 +162,8 @@ __global__ __launch_bounds__(NT) void hh_leaf_kernel(Gate gt, LeafArgs a) {
       if (g == 0 && tid == 0) a.tau[j] = tau;
       // V^T V of the leaf: v_c^T v_j = v_c(j) + (sum over rows below j of
       // v_c x_j) / (alpha - beta), for c < j (v_c(j) is the owner's row)
-      if (a.gram && g == 0 && tid < j) a.gram[tid + j * a.ldg] = sRow[tid] + sTot[tid] / inv;
+      if (tid < j) sGm[tid][j] = sRow[tid] + sTot[tid] / inv;
+      if (tid == 0) sTauL[j] = tau;
       // the reflector's action on each later column, formed once per column
       if (tid < IB) sF[tid] = (tid > j && tid < ib) ? tau * (sRow[tid] + sTot[tid] / inv) : 0.0;
       __syncthreads();
@@ -182,6 +186,35 @@ __global__ __launch_bounds__(NT) void hh_leaf_kernel(Gate gt, LeafArgs a) {
     for (int c = 0; c < IB; ++c)
       if (c < ib) a.A[r + (long)c * a.lda] = x[c];
   }
+  // T of the leaf by the UT transform, T^{-1} = diag(1/tau) + striu(V^T V)
+  // (a zero tau decouples its index: its row and column of T are zero), by
+  // one wave of workgroup 0
+  if (a.tout && g == 0 && tid < 64) {
+    if (lane < IB) {
+#pragma unroll
+      for (int rr = 0; rr < IB; ++rr) {
+        double v = 0.0;
+        if (lane < ib && rr < ib && rr <= lane) {
+          const double tr = sTauL[rr], tc = sTauL[lane];
+          if (tr == 0.0 || tc == 0.0) v = (rr == lane) ? 1.0 : 0.0;
+          else if (rr == lane) v = 1.0 / tc;
+          else v = sGm[rr][lane];
+        }
+        sGm[rr][lane] = v;
+      }
+    }
+    double ty[W32];
+    wave_inv_upper32(&sGm[0][0], IB + 1, ty, ib);
+    if (lane < ib) {
+#pragma unroll
+      for (int rr = 0; rr < IB; ++rr) {
+        if (rr < ib) {
+          const double v = (rr == lane && sTauL[lane] == 0.0) ? 0.0 : ty[rr];
+          a.tout[rr + (long)lane * a.ldt] = v;
+        }
+      }
+    }
+  }
 }
 
 int leaf_groups(long mi) {
@@ -197,7 +230,7 @@ size_t hh_leaf_records_bytes(i64 mi) {
 }
 
 int launch_hh_leaf(double* A, i64 lda, i64 mi, int ib, double* tau, uint64_t* rec,
-                   size_t rec_bytes, int* status, hipStream_t st, double* gram, i64 ldg) {
+                   size_t rec_bytes, int* status, hipStream_t st, double* tout, i64 ldt) {
   if (mi <= 0 || ib <= 0) return QRCP_OK;
   if (ib > IB) return QRCP_ERR_UNSUPPORTED;
   const int G = leaf_groups(mi);
@@ -205,7 +238,7 @@ int launch_hh_leaf(double* A, i64 lda, i64 mi, int ib, double* tau, uint64_t* re
   const size_t need = hh_leaf_records_bytes(mi);
   if (need > rec_bytes) return QRCP_ERR_WORKSPACE;
   QRCP_TRY(launch_fill_u64(rec, (i64)(need / 8), SENT, st));
-  LeafArgs args{A, (long)lda, (long)mi, ib, tau, rec, status, gram, (long)ldg};
+  LeafArgs args{A, (long)lda, (long)mi, ib, tau, rec, status, tout, (long)ldt};
   Gate gt = current_gate();
   void* params[] = {&gt, &args};
   QRCP_TRY(launch_resident((const void*)hh_leaf_kernel, dim3(G), dim3(NT), params, 0, st));

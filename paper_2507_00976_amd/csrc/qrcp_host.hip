@@ -24,8 +24,8 @@ namespace qrcp {
 
 size_t hh_leaf_records_bytes(i64 mi);
 int launch_hh_leaf(double* A, i64 lda, i64 mi, int ib, double* tau, uint64_t* rec,
-                   size_t rec_bytes, int* status, hipStream_t st, double* gram = nullptr,
-                   i64 ldg = 0);
+                   size_t rec_bytes, int* status, hipStream_t st, double* tout = nullptr,
+                   i64 ldt = 0);
 
 static thread_local std::string g_last_error;
 
@@ -312,18 +312,12 @@ int apply_qt_clean(const double* Y, i64 mi, int k, i64 ldy, const double* tau, d
   return apply_qt_rows(Y, 0, mi, k, ldy, C, nc, ldc, prec, W2, st);
 }
 
-// apply_qt_clean for a Householder leaf whose kernel left the strict upper
-// triangle of Y^T Y in G: T from the UT transform without the Gram product.
-int apply_qt_leaf(const double* Y, i64 mi, int k, i64 ldy, const double* tau, double* C, i64 nc,
-                  i64 ldc, double* G, double* T, i64 ldk, double* W, double* W2, double* split,
+// apply_qt_clean for a Householder leaf whose kernel left the T of its
+// compact WY form in T (no Gram product, no separate triangular inverse).
+int apply_qt_leaf(const double* Y, i64 mi, int k, i64 ldy, double* C, i64 nc, i64 ldc,
+                  const double* T, i64 ldk, double* W, double* W2, double* split,
                   size_t split_bytes, hipStream_t st) {
   if (k <= 0 || mi <= 0 || nc <= 0) return QRCP_OK;
-  {
-    ProfScope ps(kStLarft, 0.0, st);
-    QRCP_TRY(launch_ut_tinv(G, ldk, tau, k, st));
-    QRCP_TRY(launch_trinv_upper(G, ldk, k, T, ldk, st));
-    QRCP_TRY(launch_ut_zero_diag(T, ldk, tau, k, st));
-  }
   QRCP_TRY(apply_qt_wt(Y, mi, k, ldy, T, ldk, C, nc, ldc, Prec::F64, W, W2, split, split_bytes, st));
   return apply_qt_rows(Y, 0, mi, k, ldy, C, nc, ldc, Prec::F64, W2, st);
 }
@@ -658,13 +652,12 @@ int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
         const int ib = std::min(32, kmax - s2);
         double* Al = Ablk + s2 + (i64)s2 * lda;
         QRCP_TRY(launch_hh_leaf(Al, lda, mi - s2, ib, tau + s + s2, w.hrec, w.hrec_bytes, w.status, st,
-                                w.G, b));
+                                w.Rc, b));
         if (s2 + ib < kmax) {
           QRCP_TRY(launch_copy2d(Al, lda, w.tmp, m, mi - s2, ib, st));
           QRCP_TRY(launch_unit_lower(Al, lda, ib, w.tmp, m, st));
-          QRCP_TRY(apply_qt_leaf(w.tmp, mi - s2, ib, m, tau + s + s2, Al + (i64)ib * lda,
-                                 kmax - s2 - ib, lda, w.G, w.Rc, b, w.W, w.W2, w.split, kSplitBytes,
-                                 st));
+          QRCP_TRY(apply_qt_leaf(w.tmp, mi - s2, ib, m, Al + (i64)ib * lda, kmax - s2 - ib, lda, w.Rc,
+                                 b, w.W, w.W2, w.split, kSplitBytes, st));
         }
       }
       {
@@ -1057,13 +1050,13 @@ int qrcp_geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, int64_
         const int ib = (int)std::min<i64>(IB, kb - s2);
         double* Al = Ap + s2 + s2 * lda;
         QRCP_TRY(launch_hh_leaf(Al, lda, mi - s2, ib, tau + s + s2, w.rec, w.rec_bytes, w.status, st,
-                                w.Gl, 32));
+                                w.Tl, 32));
         if (s2 + ib < kb) {
           // clean copy of the leaf's reflectors, then update the rest of the panel
           QRCP_TRY(launch_copy2d(Al, lda, w.Yl, m, mi - s2, ib, st));
           QRCP_TRY(launch_unit_lower(Al, lda, ib, w.Yl, m, st));
-          QRCP_TRY(apply_qt_leaf(w.Yl, mi - s2, ib, m, tau + s + s2, Al + ib * lda, kb - s2 - ib, lda,
-                                 w.Gl, w.Tl, 32, w.Wl, w.W2l, w.split2, kSplitBytesSmall, st));
+          QRCP_TRY(apply_qt_leaf(w.Yl, mi - s2, ib, m, Al + ib * lda, kb - s2 - ib, lda, w.Tl, 32, w.Wl,
+                                 w.W2l, w.split2, kSplitBytesSmall, st));
         }
       }
     }
