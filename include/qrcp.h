@@ -142,7 +142,7 @@ int qrcp_factor_async(double* A, int64_t m, int64_t n, int64_t lda, int64_t bloc
  * with the same kernels, so the results equal qrcp_factor's bitwise.
  * Arguments, outputs and errors as qrcp_factor; sizes whose
  * qrcp_workspace_size() exceeds the array return QRCP_ERR_WORKSPACE before any
- * launch (e.g. m = 4096, n = 1024, b = 64 needs 155 MiB and fits; 4096 x 4096
+ * launch (e.g. m = 4096, n = 1024, b = 64 needs 159 MiB and fits; 4096 x 4096
  * at b = 256 does not).  All calls on one GPU share its array: calls that
  * overlap in time on one GPU (two host threads, or two streams) race and give
  * undefined results; serialize them.
