@@ -299,18 +299,31 @@ __device__ __forceinline__ void gemm_vec_body(const GemmArgs& g) {
   const long qa = ARS * aRs + AKS * aKs, qb = BRS * bRs + BKS * bKs;
 
   bool cinit = !g.partial && g.alpha == 1.0 && g.beta == 1.0;
+  // a tile inside C: its loads and stores need no bounds checks (the loads of
+  // the C tile then all go out before the first wait)
+  const bool interior = i0 + BM <= M && j0 + BN <= N;
   d4v acc[FM][FN];
+  if (cinit && interior) {
+    const double* cb = g.C + (i0 + wm * WM + (lane & 15)) + (long)(j0 + wn * WN) * g.ldc;
 #pragma unroll
-  for (int a = 0; a < FM; ++a) {
-    const long gi = i0 + wm * WM + a * 16 + (lane & 15);
+    for (int a = 0; a < FM; ++a)
 #pragma unroll
-    for (int b = 0; b < FN; ++b) {
-      acc[a][b] = MF::zero();
-      if (cinit) {
+      for (int b = 0; b < FN; ++b)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const long gj = j0 + wn * WN + b * 16 + MF::row(lane, r);
-          if (gi < M && gj < N) acc[a][b][r] = g.C[gi + gj * g.ldc];
+        for (int r = 0; r < 4; ++r) acc[a][b][r] = cb[a * 16 + (long)(b * 16 + MF::row(lane, r)) * g.ldc];
+  } else {
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+      const long gi = i0 + wm * WM + a * 16 + (lane & 15);
+#pragma unroll
+      for (int b = 0; b < FN; ++b) {
+        acc[a][b] = MF::zero();
+        if (cinit) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const long gj = j0 + wn * WN + b * 16 + MF::row(lane, r);
+            if (gi < M && gj < N) acc[a][b][r] = g.C[gi + gj * g.ldc];
+          }
         }
       }
     }
@@ -381,6 +394,16 @@ __device__ __forceinline__ void gemm_vec_body(const GemmArgs& g) {
     }
   }
 
+  if (cinit && interior) {
+    double* cb = g.C + (i0 + wm * WM + (lane & 15)) + (long)(j0 + wn * WN) * g.ldc;
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cb[a * 16 + (long)(b * 16 + MF::row(lane, r)) * g.ldc] = acc[a][b][r];
+    return;
+  }
 #pragma unroll
   for (int a = 0; a < FM; ++a) {
     const long gi = i0 + wm * WM + a * 16 + (lane & 15);
