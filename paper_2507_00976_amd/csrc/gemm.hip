@@ -394,14 +394,18 @@ __device__ __forceinline__ void gemm_vec_body(const GemmArgs& g) {
     }
   }
 
-  if (cinit && interior) {
-    double* cb = g.C + (i0 + wm * WM + (lane & 15)) + (long)(j0 + wn * WN) * g.ldc;
+  if (interior && (g.partial || cinit || g.beta == 0.0)) {
+    // a split-K partial, an accumulated C, or C = alpha A B: plain stores
+    const long ld = g.partial ? (long)M : g.ldc;
+    const double sc = (g.partial || cinit) ? 1.0 : g.alpha;
+    double* cb = (g.partial ? g.partial + (long)blockIdx.z * M * N : g.C) + (i0 + wm * WM + (lane & 15)) +
+                 (long)(j0 + wn * WN) * ld;
 #pragma unroll
     for (int a = 0; a < FM; ++a)
 #pragma unroll
       for (int b = 0; b < FN; ++b)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) cb[a * 16 + (long)(b * 16 + MF::row(lane, r)) * g.ldc] = acc[a][b][r];
+        for (int r = 0; r < 4; ++r) cb[a * 16 + (long)(b * 16 + MF::row(lane, r)) * ld] = sc * acc[a][b][r];
     return;
   }
 #pragma unroll
