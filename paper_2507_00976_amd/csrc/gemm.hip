@@ -330,17 +330,26 @@ __device__ __forceinline__ void gemm_vec_body(const GemmArgs& g) {
   }
 
   double2 ra[PA], rb[PB];
+  // an interior tile whose K range is whole chunks loads without checks
+  const bool full = interior && (kend - kbeg) % BK == 0;
   auto load_tiles = [&](long k0) {
     const long rem = kend - k0;
+    if (full) {
 #pragma unroll
-    for (int q = 0; q < PA; ++q) {
-      const bool ok = (i0 + ar0 + q * ARS) < M && (ak0 + q * AKS) < rem;
-      ra[q] = ok ? *reinterpret_cast<const double2*>(pa + q * qa) : double2{0.0, 0.0};
-    }
+      for (int q = 0; q < PA; ++q) ra[q] = *reinterpret_cast<const double2*>(pa + q * qa);
 #pragma unroll
-    for (int q = 0; q < PB; ++q) {
-      const bool ok = (j0 + br0 + q * BRS) < N && (bk0 + q * BKS) < rem;
-      rb[q] = ok ? *reinterpret_cast<const double2*>(pb + q * qb) : double2{0.0, 0.0};
+      for (int q = 0; q < PB; ++q) rb[q] = *reinterpret_cast<const double2*>(pb + q * qb);
+    } else {
+#pragma unroll
+      for (int q = 0; q < PA; ++q) {
+        const bool ok = (i0 + ar0 + q * ARS) < M && (ak0 + q * AKS) < rem;
+        ra[q] = ok ? *reinterpret_cast<const double2*>(pa + q * qa) : double2{0.0, 0.0};
+      }
+#pragma unroll
+      for (int q = 0; q < PB; ++q) {
+        const bool ok = (j0 + br0 + q * BRS) < N && (bk0 + q * BKS) < rem;
+        rb[q] = ok ? *reinterpret_cast<const double2*>(pb + q * qb) : double2{0.0, 0.0};
+      }
     }
     pa += BK * aKs;
     pb += BK * bKs;
