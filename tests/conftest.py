@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests are skipped (not failed) where no GPU is visible, so that a plain
-    # `pytest` on a CPU machine runs the CPU tier; `-m gpu` on the GPU machine runs them.
+    # `pytest` on a machine without a GPU runs the CPU tier; `-m gpu` runs them on an MI355X.
     try:
         import torch
         has_gpu = torch.cuda.is_available()
