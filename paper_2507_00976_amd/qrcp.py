@@ -160,7 +160,9 @@ def _cm(a: torch.Tensor, name: str, dtype=torch.float64):
     if not a.is_cuda:
         raise ValueError(f"{name} must be a CUDA/HIP tensor")
     m, n = a.shape
-    if n > 1 and m > 0 and a.stride(0) != 1:
+    # the row stride matters only with two or more rows and columns (torch keeps
+    # any stride on a dimension of size 1)
+    if n > 1 and m > 1 and a.stride(0) != 1:
         raise ValueError(f"{name} must be column-major (stride(0) == 1); use colmajor()")
     ld = a.stride(1) if n > 1 else max(m, 1)
     return a.data_ptr(), m, n, max(ld, max(m, 1))

@@ -64,6 +64,17 @@ def test_shapes(Q, m, n, b, gamma):
     compare(a, got, ref, tau_rtol=1e-9)
 
 
+@pytest.mark.parametrize("m,n,b", [(1, 1, 1), (5, 1, 1), (1, 5, 2), (2, 2, 1), (33, 3, 2), (3, 33, 8),
+                                   (64, 64, 1), (17, 40, 40), (40, 17, 64)])
+def test_degenerate_shapes(Q, m, n, b):
+    # single rows or columns, one-column blocks (d = 2), blocks wider than the
+    # matrix, sketches with more rows than the matrix
+    a = W.gaussian(m, n, 100 + m + 7 * n + 11 * b)
+    ref = O.bqrrp(a, b, 1.25, 42, 0.0)
+    got = run_gpu(Q, a, b)
+    compare(a, got, ref)
+
+
 def test_cholqr2_option(Q):
     a, cfg = W.config_matrix("c1")
     ref = O.bqrrp(a, 64, 1.25, 42, 0.0, cholqr_passes=2)

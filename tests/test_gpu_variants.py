@@ -239,3 +239,19 @@ def test_geqp3_on_sketch_businger_golub(Q):
             agree += 1
             np.testing.assert_allclose(np.abs(np.diag(got.a)), sig, rtol=1e-10)
     assert agree >= 7, agree
+
+
+@pytest.mark.parametrize("m,n,b", [(1, 1, 1), (1, 5, 2), (5, 1, 1), (3, 33, 8), (33, 3, 2), (40, 17, 64)])
+@pytest.mark.parametrize("variant", ["householder_panel", "geqp3_on_sketch"])
+def test_variants_degenerate_shapes(Q, m, n, b, variant):
+    """The Householder panel and GEQP3 on the sketch on single rows or columns,
+    one-column blocks and blocks wider than the matrix."""
+    a = W.gaussian(m, n, seed=200 + m + 7 * n + 11 * b)
+    if variant == "householder_panel":
+        ref = O.bqrrp(a, b, 1.25, 42, 0.0, qr_tall="geqrf")
+        got = run_gpu(Q, a, b, 1.25, 42, 0.0, qr_tall=1)
+    else:
+        ref = O.bqrrp(a, b, 1.25, 42, 0.0, qrcp_wide="geqp3")
+        got = run_gpu(Q, a, b, 1.25, 42, 0.0, qrcp_wide=1)
+    assert got.rank == min(m, n)
+    check_against(a, got, ref)
