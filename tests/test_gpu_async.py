@@ -42,7 +42,8 @@ def _same(x, y):
 
 
 @pytest.mark.parametrize("case", ["full", "ragged", "exact_rank", "gap_exit", "wide", "trunc",
-                                  "hqr", "hqr_rank", "geqp3", "cholqr2", "cholqr2_rank", "single"])
+                                  "hqr", "hqr_rank", "geqp3", "cholqr2", "cholqr2_rank", "single",
+                                  "one_row", "one_col", "b1"])
 def test_async_matches_blocking(Q, case):
     kw, tol, b = {}, 0.0, 32
     if case == "full":
@@ -71,6 +72,12 @@ def test_async_matches_blocking(Q, case):
         a, tol, kw = W.lowrank(400, 200, 50, 0.0, seed=10), 1e-12, {"cholqr_passes": 2}
     elif case == "single":
         a, b = W.usv(256, 100, W.spectrum("geometric", 100, lo=1e-6), seed=11), 128
+    elif case == "one_row":
+        a, b = W.gaussian(1, 5, seed=12), 2
+    elif case == "one_col":
+        a, b = W.gaussian(5, 1, seed=13), 1
+    elif case == "b1":
+        a, b = W.gaussian(64, 40, seed=14), 1
     x, y = _pair(Q, a, b, 1.25, 42, tol, **kw)
     _same(x, y)
 
