@@ -80,6 +80,14 @@ __device__ __forceinline__ void wave_lds_sync() {
 __device__ __forceinline__ uint64_t dbits(double x) { return __double_as_longlong(x); }
 __device__ __forceinline__ double bitsd(uint64_t x) { return __longlong_as_double((long long)x); }
 
+// FP64 -> FP32 (RNE) -> BF16 (RNE) bits.
+__device__ __forceinline__ unsigned short to_bf16_bits(double x) {
+  float f = (float)x;
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
 __device__ __forceinline__ void store_agent(uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

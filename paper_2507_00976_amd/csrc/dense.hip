@@ -40,7 +40,10 @@ __global__ void philox_kernel(Gate gt, const uint32_t* ctr, long count, uint32_t
 }
 
 // S^T (m x d, ld): S(2p, j), S(2p+1, j) from block (j, p, 0, 0) by Box-Muller.
-__global__ void sketch_operator_kernel(Gate gt, double* St, long m, int d, long ld, uint32_t k0,
+// BITS: the entries as BF16 bits (the FP64 value rounded to FP32, then to BF16)
+// in an array of 16-bit words, for the BF16 sketch product.
+template <bool BITS>
+__global__ void sketch_operator_kernel(Gate gt, void* out, long m, int d, long ld, uint32_t k0,
                                        uint32_t k1) {
   QRCP_GATE(gt);
   const long j = blockIdx.x * (long)blockDim.x + threadIdx.x;
@@ -53,16 +56,34 @@ __global__ void sketch_operator_kernel(Gate gt, double* St, long m, int d, long 
   const double u2 = (double)(w23 >> 11) * 0x1p-53;
   const double rad = sqrt(-2.0 * log(u1));
   const double ang = (2.0 * 3.141592653589793) * u2;
-  St[j + (long)(2 * p) * ld] = rad * cos(ang);
-  if (2 * p + 1 < d) St[j + (long)(2 * p + 1) * ld] = rad * sin(ang);
+  const double s0 = rad * cos(ang);
+  const double s1 = rad * sin(ang);
+  if (BITS) {
+    unsigned short* St = static_cast<unsigned short*>(out);
+    St[j + (long)(2 * p) * ld] = to_bf16_bits(s0);
+    if (2 * p + 1 < d) St[j + (long)(2 * p + 1) * ld] = to_bf16_bits(s1);
+  } else {
+    double* St = static_cast<double*>(out);
+    St[j + (long)(2 * p) * ld] = s0;
+    if (2 * p + 1 < d) St[j + (long)(2 * p + 1) * ld] = s1;
+  }
 }
 
 int launch_sketch_operator(double* St, i64 m, int d, i64 ldst, uint64_t seed, hipStream_t st) {
   if (m <= 0 || d <= 0) return QRCP_OK;
   dim3 grid((m + 255) / 256, (d + 1) / 2);
-  hipLaunchKernelGGL(sketch_operator_kernel, grid, dim3(256), 0, st, current_gate(), St, m, d, ldst,
-                     (uint32_t)seed, (uint32_t)(seed >> 32));
+  hipLaunchKernelGGL(sketch_operator_kernel<false>, grid, dim3(256), 0, st, current_gate(), (void*)St, m, d,
+                     ldst, (uint32_t)seed, (uint32_t)(seed >> 32));
   QRCP_LAUNCHED("sketch_operator");
+  return QRCP_OK;
+}
+
+int launch_sketch_operator_bf16(unsigned short* St, i64 m, int d, i64 ldst, uint64_t seed, hipStream_t st) {
+  if (m <= 0 || d <= 0) return QRCP_OK;
+  dim3 grid((m + 255) / 256, (d + 1) / 2);
+  hipLaunchKernelGGL(sketch_operator_kernel<true>, grid, dim3(256), 0, st, current_gate(), (void*)St, m, d,
+                     ldst, (uint32_t)seed, (uint32_t)(seed >> 32));
+  QRCP_LAUNCHED("sketch_operator_bf16");
   return QRCP_OK;
 }
 

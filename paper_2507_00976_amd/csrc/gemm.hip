@@ -57,14 +57,6 @@ struct Mfma<float> {
   __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-// FP64 -> FP32 (RNE) -> BF16 (RNE) bits.
-__device__ __forceinline__ unsigned short to_bf16_bits(double x) {
-  float f = (float)x;
-  unsigned u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-
 template <typename T>
 __device__ __forceinline__ T cvt(double x) {
   return (T)x;
@@ -526,6 +518,109 @@ __global__ __launch_bounds__(256) void gemm_bf16_tn_kernel(Gate gt, GemmArgs g) 
   }
 }
 
+// M^sk = S A for the BF16 sketch: S arrives as BF16 bits (S^T, m x d, ld lds a
+// multiple of 32, generated so), A (m x n, FP64) is rounded to BF16 on load,
+// and the products accumulate in FP32 on the matrix cores.  A workgroup holds
+// all d rows of a 64-column strip of M^sk, so each element of A is read once
+// (the product is bound by that read); grid.y splits K, and the partials are
+// summed in FP32 in a fixed order.  MB row blocks of 16 cover d; wave w owns
+// the strip's columns 16 w .. 16 w + 15.
+template <int MB>
+__global__ __launch_bounds__(256) void sketch_bf16_kernel(Gate gt, const unsigned short* S, long lds,
+                                                          const double* A, long lda, int d, int n, long m,
+                                                          long kchunk, double* P, double* C, long ldc) {
+  QRCP_GATE(gt);
+  constexpr int BK = 32, LK = BK + 8, RS = MB * 16;
+  constexpr int SQ = (RS * 4 + 255) / 256;  // 16-byte pieces of the S chunk per thread
+  __shared__ __align__(16) unsigned short sS[RS][LK];
+  __shared__ __align__(16) unsigned short sA[64][LK];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const long j0 = (long)blockIdx.x * 64;
+  const long kbeg = (long)blockIdx.y * kchunk;
+  const long kend = min(m, kbeg + kchunk);
+  f4v acc[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) acc[mb] = f4v{0.f, 0.f, 0.f, 0.f};
+  uint4 rs[SQ];
+  double ra[8];
+  const int aj = tid >> 2, ak = (tid & 3) * 8;  // A: column j0 + aj, k = k0 + ak .. k0 + ak + 7
+  const bool jok = j0 + aj < n;
+  // the chunk at k0 into registers (S rows past d read as zero; S words past
+  // kend are masked when stored, A words past kend are not read)
+  auto load = [&](long k0) {
+#pragma unroll
+    for (int q = 0; q < SQ; ++q) {
+      const int seg = tid + 256 * q, row = seg >> 2, part = seg & 3;
+      rs[q] = (seg < RS * 4 && row < d)
+                  ? *reinterpret_cast<const uint4*>(S + (long)row * lds + k0 + part * 8)
+                  : uint4{0u, 0u, 0u, 0u};
+    }
+    const double* ap = A + (j0 + aj) * lda + k0 + ak;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) ra[e] = (jok && k0 + ak + e < kend) ? ap[e] : 0.0;
+  };
+  auto store = [&](long k0) {
+#pragma unroll
+    for (int q = 0; q < SQ; ++q) {
+      const int seg = tid + 256 * q, row = seg >> 2, part = seg & 3;
+      if (seg < RS * 4) {
+        uint4 v = rs[q];
+        const long kk = k0 + part * 8;
+        if (kk + 8 > kend) {
+          unsigned* u = reinterpret_cast<unsigned*>(&v);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const unsigned lo = (kk + 2 * e < kend) ? (u[e] & 0xFFFFu) : 0u;
+            const unsigned hi = (kk + 2 * e + 1 < kend) ? (u[e] & 0xFFFF0000u) : 0u;
+            u[e] = lo | hi;
+          }
+        }
+        *reinterpret_cast<uint4*>(&sS[row][part * 8]) = v;
+      }
+    }
+    unsigned h[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      h[e] = (unsigned)to_bf16_bits(ra[2 * e]) | ((unsigned)to_bf16_bits(ra[2 * e + 1]) << 16);
+    *reinterpret_cast<uint4*>(&sA[aj][ak]) = uint4{h[0], h[1], h[2], h[3]};
+  };
+  if (kbeg < kend) {
+    load(kbeg);
+    for (long k0 = kbeg; k0 < kend; k0 += BK) {
+      __syncthreads();  // the previous chunk's LDS reads are done
+      store(k0);
+      __syncthreads();
+      if (k0 + BK < kend) load(k0 + BK);  // in flight during this chunk's products
+#pragma unroll
+      for (int ks = 0; ks < BK; ks += 16) {
+        const int kq = ks + 4 * (lane >> 4);
+        const unsigned short* pb = &sA[w * 16 + (lane & 15)][kq];
+        const s4v bf = s4v{(short)pb[0], (short)pb[1], (short)pb[2], (short)pb[3]};
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          const unsigned short* pa = &sS[mb * 16 + (lane & 15)][kq];
+          const s4v af = s4v{(short)pa[0], (short)pa[1], (short)pa[2], (short)pa[3]};
+          acc[mb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bf, af, acc[mb], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // D(i, j): row 16 mb + lane % 16 of M^sk, column 16 w + 4 (lane / 16) + r of the strip
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+    const int gi = mb * 16 + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const long gj = j0 + w * 16 + 4 * (lane >> 4) + r;
+      if (gi < d && gj < n) {
+        const double v = (double)acc[mb][r];
+        if (P) P[(long)blockIdx.y * d * n + gi + gj * d] = v;
+        else C[gi + gj * ldc] = v;
+      }
+    }
+  }
+}
+
 // Fixed-order reduction of split-K partials: C = alpha * sum_z P_z + beta * C.
 // For the BF16 path (fp32_sum) the partials are summed in FP32 so the whole
 // accumulation stays FP32.
@@ -655,6 +750,44 @@ static void launch_shape(const GemmArgs& g, int cfg, int splits, hipStream_t st)
 }
 
 size_t gemm_splitk_bytes(long M, long N, int splits) { return (size_t)M * N * splits * sizeof(double); }
+
+int launch_sketch_bf16(const double* A, i64 m, i64 n, i64 lda, int d, uint64_t seed, double* Msk, i64 ldmsk,
+                       void* sbuf, size_t sbuf_bytes, double* split, size_t split_bytes, hipStream_t st) {
+  if (d < 1 || d > 320 || m <= 0 || n <= 0) return QRCP_ERR_UNSUPPORTED;
+  const long lds = (m + 31) / 32 * 32;  // whole 32-row chunks of S^T stay inside the buffer
+  if ((size_t)lds * d * sizeof(unsigned short) > sbuf_bytes) return QRCP_ERR_UNSUPPORTED;
+  QRCP_TRY(launch_sketch_operator_bf16(static_cast<unsigned short*>(sbuf), m, d, lds, seed, st));
+  // about four workgroups per compute unit, at least 256 rows of K per split,
+  // and the partials within the split area
+  const long nstrips = (n + 63) / 64;
+  long splits = std::max<long>(1, (1024 + nstrips - 1) / nstrips);
+  splits = std::min<long>(splits, std::max<long>(1, m / 256));
+  splits = std::min<long>(splits, 64);
+  while (splits > 1 && (size_t)splits * d * n * sizeof(double) > split_bytes) --splits;
+  const long kchunk = ((m + splits - 1) / splits + 31) / 32 * 32;
+  splits = (m + kchunk - 1) / kchunk;
+  double* P = splits > 1 ? split : nullptr;
+  const dim3 grid((unsigned)nstrips, (unsigned)splits);
+  const int mb = (d + 15) / 16;
+  const unsigned short* S = static_cast<const unsigned short*>(sbuf);
+  if (mb <= 5)
+    hipLaunchKernelGGL(sketch_bf16_kernel<5>, grid, dim3(256), 0, st, current_gate(), S, lds, A, (long)lda, d,
+                       (int)n, (long)m, kchunk, P, Msk, (long)ldmsk);
+  else if (mb <= 10)
+    hipLaunchKernelGGL(sketch_bf16_kernel<10>, grid, dim3(256), 0, st, current_gate(), S, lds, A, (long)lda, d,
+                       (int)n, (long)m, kchunk, P, Msk, (long)ldmsk);
+  else
+    hipLaunchKernelGGL(sketch_bf16_kernel<20>, grid, dim3(256), 0, st, current_gate(), S, lds, A, (long)lda, d,
+                       (int)n, (long)m, kchunk, P, Msk, (long)ldmsk);
+  QRCP_LAUNCHED("sketch_bf16");
+  if (P) {
+    const long dn = (long)d * n;
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((dn + 255) / 256), dim3(256), 0, st, current_gate(), P,
+                       (int)splits, d, (int)n, 1.0, 0.0, Msk, (long)ldmsk, 1);
+    QRCP_LAUNCHED("splitk_reduce");
+  }
+  return QRCP_OK;
+}
 
 // Chooses a split of K when the output has too few tiles to fill the GPU:
 // about `target` workgroups (512 by default; the W = Y^T C product of the

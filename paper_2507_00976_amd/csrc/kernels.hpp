@@ -31,6 +31,12 @@ int gemm_pick_splits(long M, long N, long K, long target = 512);
 
 // ---- sketch operator ----
 int launch_sketch_operator(double* St, i64 m, int d, i64 ldst, uint64_t seed, hipStream_t st);
+int launch_sketch_operator_bf16(unsigned short* St, i64 m, int d, i64 ldst, uint64_t seed, hipStream_t st);
+// M^sk = S A with S in BF16 (generated into sbuf) and FP32 accumulation, for
+// d <= 320; QRCP_ERR_UNSUPPORTED (nothing launched) otherwise, or when sbuf is
+// too small, so that the caller takes the general BF16 product.
+int launch_sketch_bf16(const double* A, i64 m, i64 n, i64 lda, int d, uint64_t seed, double* Msk, i64 ldmsk,
+                       void* sbuf, size_t sbuf_bytes, double* split, size_t split_bytes, hipStream_t st);
 int launch_philox(const uint32_t* ctr, i64 count, uint32_t k0, uint32_t k1, uint32_t* out,
                   hipStream_t st);
 

@@ -503,10 +503,20 @@ int factor_impl(double* A, int64_t m, int64_t n, int64_t lda, int64_t block_size
   // ---- sketch M^sk = S A (S generated once, stored transposed) ----
   if (lim > 0) {
     ProfScope ps(kStSketch, 2.0 * d * m * n, st);
-    QRCP_TRY(launch_sketch_operator(w.big, m, d, m, seed, st));
-    GemmArgs g = ga(d, (int)n, (int)m, w.big, m, A, lda, w.sk0, d);
-    g.kind = GemmKind::Sketch;
-    QRCP_TRY(gemm(true, false, o.sketch_precision ? Prec::BF16 : Prec::F64, g, w.split, kSplitBytes, st));
+    // the BF16 product holding all d rows per tile (S generated in BF16), else
+    // the general one
+    int rc = QRCP_ERR_UNSUPPORTED;
+    if (o.sketch_precision)
+      rc = launch_sketch_bf16(A, m, n, lda, d, seed, w.sk0, d, w.big,
+                              (size_t)std::max(m * (i64)d, m * n) * sizeof(double), w.split, kSplitBytes, st);
+    if (rc == QRCP_ERR_UNSUPPORTED) {
+      QRCP_TRY(launch_sketch_operator(w.big, m, d, m, seed, st));
+      GemmArgs g = ga(d, (int)n, (int)m, w.big, m, A, lda, w.sk0, d);
+      g.kind = GemmKind::Sketch;
+      QRCP_TRY(gemm(true, false, o.sketch_precision ? Prec::BF16 : Prec::F64, g, w.split, kSplitBytes, st));
+    } else {
+      QRCP_TRY(rc);
+    }
     QRCP_TRY(launch_sketch_ref(w.sk0, d, d, n, w.colss, w.ref, st));
   }
 
@@ -1129,9 +1139,17 @@ int qrcp_sketch(const double* A, int64_t m, int64_t n, int64_t lda, int64_t d, u
   Carver c{(char*)workspace};
   double* St = c.take<double>((size_t)m * d);
   double* split = c.take<double>(kSketchSplitBytes / 8);
-  QRCP_TRY(launch_sketch_operator(St, m, (int)d, m, seed, st));
-  QRCP_TRY(gemm(true, false, precision ? Prec::BF16 : Prec::F64,
-                ga((int)d, (int)n, (int)m, St, m, A, lda, Msk, ldmsk), split, kSketchSplitBytes, st));
+  int rc = QRCP_ERR_UNSUPPORTED;
+  if (precision)
+    rc = launch_sketch_bf16(A, m, n, lda, (int)d, seed, Msk, ldmsk, St, (size_t)m * d * 8, split,
+                            kSketchSplitBytes, st);
+  if (rc == QRCP_ERR_UNSUPPORTED) {
+    QRCP_TRY(launch_sketch_operator(St, m, (int)d, m, seed, st));
+    QRCP_TRY(gemm(true, false, precision ? Prec::BF16 : Prec::F64,
+                  ga((int)d, (int)n, (int)m, St, m, A, lda, Msk, ldmsk), split, kSketchSplitBytes, st));
+  } else {
+    QRCP_TRY(rc);
+  }
   QRCP_HIP(hipStreamSynchronize(st));
   return QRCP_OK;
 }

@@ -53,9 +53,12 @@ def test_sketch_gemm_f64(Q, m, n, d):
     assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref)) * np.sqrt(m)
 
 
-def test_sketch_gemm_bf16(Q):
-    m, n, d = 1024, 512, 80
-    a = W.gaussian(m, n, seed=3)
+@pytest.mark.parametrize("m,n,d", [(1024, 512, 80), (3001, 700, 320), (777, 65, 33), (40000, 130, 160),
+                                   (100, 3, 321)])
+def test_sketch_gemm_bf16(Q, m, n, d):
+    # d <= 320: the product holding all d rows per tile, with ragged K (m), ragged
+    # column strips and several K splits; d = 321: the general BF16 product
+    a = W.gaussian(m, n, seed=3 + m)
     got = host(Q.sketch(dev(a), d, 7, 1))
     ref = O.sketch(a, d, 7, "bf16")
     s = O.to_bf16(O.sketch_operator(d, m, 7)).astype(np.float64)
