@@ -43,7 +43,7 @@ def _same(x, y):
 
 @pytest.mark.parametrize("case", ["full", "ragged", "exact_rank", "gap_exit", "wide", "trunc",
                                   "hqr", "hqr_rank", "geqp3", "cholqr2", "cholqr2_rank", "single",
-                                  "one_row", "one_col", "b1"])
+                                  "one_row", "one_col", "b1", "bf16_sketch"])
 def test_async_matches_blocking(Q, case):
     kw, tol, b = {}, 0.0, 32
     if case == "full":
@@ -78,6 +78,9 @@ def test_async_matches_blocking(Q, case):
         a, b = W.gaussian(5, 1, seed=13), 1
     elif case == "b1":
         a, b = W.gaussian(64, 40, seed=14), 1
+    elif case == "bf16_sketch":
+        a, kw = (W.usv(700, 400, W.spectrum("geometric", 400, lo=1e-9), seed=15),
+                 {"sketch_precision": 1, "cholqr_passes": 2})
     x, y = _pair(Q, a, b, 1.25, 42, tol, **kw)
     _same(x, y)
 
