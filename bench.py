@@ -262,7 +262,7 @@ def full_checks(torch, A0, A, jpiv, tau, rank):
     return res, orth
 
 
-def run_precision_variants(args, torch, qrcp, WD):
+def run_precision_variants(args, torch, qrcp, WD, steps=None):
     """Tall 65536 x 8192, sigma_i geometric 1 -> 1e-14: FP64, BF16 sketch, BF16 sketch + FP32
     trailing update; residual, orthogonality, |R_kk|/sigma_k and pivot agreement with FP64."""
     dev = torch.device("cuda:0")
@@ -287,7 +287,7 @@ def run_precision_variants(args, torch, qrcp, WD):
         qrcp.factor(A, b, args.gamma, 42, 0.0, workspace=ws, **opts)
         torch.cuda.synchronize()
         ts = []
-        for _ in range(max(args.steps, 1)):
+        for _ in range(max(args.steps if steps is None else steps, 1)):
             A.copy_(A0)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -311,10 +311,10 @@ def run_precision_variants(args, torch, qrcp, WD):
             f"|Rkk|/sigma_k in [{rec['rkk_over_sigma']['min']:.3g}, "
             f"{rec['rkk_over_sigma']['max']:.3g}], pivots vs fp64 {agree}")
     out["value"] = out["variants"]["fp64"]["gflops"]
-    print(json.dumps(out), flush=True)
+    return out
 
 
-def run_lowrank(args, torch, qrcp, WD):
+def run_lowrank(args, torch, qrcp, WD, steps=None):
     """32768^2 = rank-4096 Gaussian product + 1e-12 noise, b = 512, d = 640, tol = 1e-10:
     detected rank, runtime, truncated-canonical GFLOP/s."""
     dev = torch.device("cuda:0")
@@ -328,7 +328,7 @@ def run_lowrank(args, torch, qrcp, WD):
     qrcp.factor(A, b, args.gamma, 42, tol, workspace=ws)
     torch.cuda.synchronize()
     ts = []
-    for _ in range(max(args.steps, 1)):
+    for _ in range(max(args.steps if steps is None else steps, 1)):
         A.copy_(A0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -350,7 +350,7 @@ def run_lowrank(args, torch, qrcp, WD):
                       "m": m, "n": n, "block_size": b, "sketch_rows": d, "tol": tol}}
     log(f"lowrank: {dt * 1e3:.1f} ms, rank {rank} (expected {r}), "
         f"{fl / dt / 1e9:.1f} truncated GFLOP/s, sampled residual {check:.2e}")
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def serving_run(args, torch, qrcp, WD, nreq, pool, loads):
@@ -476,6 +476,9 @@ def main():
     ap.add_argument("--seed", type=int, default=20250702)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
     ap.add_argument("--no-geqrf", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the compact runs of the precision (65536x8192) and rank-detection "
+                         "(32768^2) workloads in the headline line")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the compact serving run of the default line")
     ap.add_argument("--breakdown", action="store_true", help="extra run timing every stage")
@@ -527,13 +530,15 @@ def main():
     from workloads import device as WD
 
     if args.workload == "precision":
-        return run_precision_variants(args, torch, qrcp, WD)
+        print(json.dumps(run_precision_variants(args, torch, qrcp, WD)), flush=True)
+        return
     if args.workload == "serving":
         return run_serving(args, torch, qrcp, WD)
     if args.workload == "lowrank":
         if args.block == 256:
             args.block = 512
-        return run_lowrank(args, torch, qrcp, WD)
+        print(json.dumps(run_lowrank(args, torch, qrcp, WD)), flush=True)
+        return
 
     dev = torch.device("cuda:0")
     m = n = args.n
@@ -761,6 +766,24 @@ def main():
         }
         log(f"first block vs oracle: pivots identical "
             f"{out['first_block_parity']['pivots_identical']}, R rows max err {rerr:.2e} ||A||_F")
+
+    # compact runs of the other two workloads (one timed factorization each),
+    # so that their figures reach the same line; `--workload precision|lowrank`
+    # runs them in full
+    if not args.no_configs and (m, n, b) == (16384, 16384, 256) and not args.sketch_bf16:
+        del A, A0, ws
+        torch.cuda.empty_cache()
+        pr = run_precision_variants(args, torch, qrcp, WD, steps=1)
+        out["precision_65536x8192"] = {
+            k: {"ms": v["ms"], "gflops": v["gflops"], "residual": v["residual"],
+                "orthogonality": v["orthogonality"], "pivot_agreement_with_fp64": v["pivot_agreement_with_fp64"]}
+            for k, v in pr["variants"].items()}
+        torch.cuda.empty_cache()
+        lr = run_lowrank(args, torch, qrcp, WD, steps=1)
+        out["rank_detection_32768"] = {k: lr[k] for k in ("ms", "rank", "rank_expected",
+                                                          "sampled_residual_first_rank_columns")}
+        out["rank_detection_32768"]["truncated_gflops"] = lr["value"]
+        torch.cuda.empty_cache()
 
     print(json.dumps(out), flush=True)
 
