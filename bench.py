@@ -478,7 +478,7 @@ def main():
     ap.add_argument("--no-geqrf", action="store_true")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the compact runs of the precision (65536x8192) and rank-detection "
-                         "(32768^2) workloads in the headline line")
+                         "(32768^2) workloads and the update kernel's lone run (for profiled runs)")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the compact serving run of the default line")
     ap.add_argument("--breakdown", action="store_true", help="extra run timing every stage")
@@ -623,7 +623,8 @@ def main():
     # the first block's deferred launch (rows b..m, k = b, the n - b trailing
     # columns), C in A's storage (its contents are no longer needed); the
     # timed factorization runs it beside the next block's sketch QR
-    if m > b and n > b and not args.sketch_bf16:
+    # (left out of the profiled commands: --no-configs, --no-check)
+    if m > b and n > b and not args.sketch_bf16 and not args.no_configs and not args.no_check:
         mi, nc = m - b, n - b
         gen = torch.Generator(device=dev).manual_seed(args.seed + 99)
         Yal = qrcp.colmajor(torch.randn(mi, b, generator=gen, dtype=torch.float64, device=dev) * 0.01)
@@ -770,7 +771,8 @@ def main():
     # compact runs of the other two workloads (one timed factorization each),
     # so that their figures reach the same line; `--workload precision|lowrank`
     # runs them in full
-    if not args.no_configs and (m, n, b) == (16384, 16384, 256) and not args.sketch_bf16:
+    if (not args.no_configs and (m, n, b) == (16384, 16384, 256) and args.matrix == "usv"
+            and not args.no_check and not args.sketch_bf16):
         del A, A0, ws
         torch.cuda.empty_cache()
         pr = run_precision_variants(args, torch, qrcp, WD, steps=1)
